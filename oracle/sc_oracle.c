@@ -1,0 +1,246 @@
+/*
+ * Sutton-Chen oracle: a plain, slow, double-precision CPU implementation of
+ * what the cluster-MD hot path computes.  TEST INFRASTRUCTURE ONLY: it is
+ * called by the test suite, by the smoke check and by the CPU-baseline leg of
+ * the benchmark, never by the product library, and it shares no code with it.
+ *
+ * Every sum below is the literal definition: a double loop over ordered pairs
+ * (i, j != i) in index order, no blocking, no Newton-3 halving, no fusion.
+ * Floating point is IEEE double with round-to-nearest; build without
+ * -ffast-math.  OpenMP (when enabled) only splits the outer i loop; each
+ * per-atom sum is still taken over j in increasing order.
+ *
+ * Paper: Yakubovich, Sushko, Schramm, Solov'yov, "Kinetics of liquid-solid
+ * phase transition in large nickel clusters" (arXiv:1210.3559).
+ *   - potential energy:       Sec. 2.1 "Interaction potential for nickel
+ *                             atoms", Eq. (SC)
+ *   - per-atom density:       Sec. 2.1, Eq. (rho)
+ *   - Ni parameter set:       Sec. 2.1, text after Eq. (rho)
+ *   - forces:                 -grad U of Eq. (SC); the paper states only that
+ *                             the density sweep precedes the force sweep
+ *                             (Sec. 2, "Computational approach").  The
+ *                             closed form is derived at sco_forces below.
+ *   - Verlet integrator, 1 fs (Sec. 2, "Computational approach", last
+ *     paragraph);
+ *     read as velocity-Verlet.
+ *   - Berendsen thermostat with a linear target ramp: not in the paper (the
+ *     paper uses Langevin); it is the deterministic thermostat of the
+ *     cooling workloads this library runs.
+ *   - Shifted cutoff: not in the paper (which runs all-pairs and calls a
+ *     cutoff future work); both power sums are shifted to zero at rc and the
+ *     forces are the exact gradient of that shifted energy.
+ */
+#include "sc_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* 1 u*A^2/fs^2 in eV (CODATA 2018: e = 1.602176634e-19 J, u = 1.66053906660e-27 kg). */
+#define SCO_KE_EV_PER_U_A2_FS2 103.64269652680505
+/* Boltzmann constant in eV/K (SI 2019 exact k_B divided by e). */
+#define SCO_KB_EV_PER_K 8.617333262145179e-05
+
+double sco_ke_conversion(void) { return SCO_KE_EV_PER_U_A2_FS2; }
+double sco_kb(void) { return SCO_KB_EV_PER_K; }
+
+static void set_threads(int nthreads) {
+#ifdef _OPENMP
+    omp_set_num_threads(nthreads > 0 ? nthreads : 1);
+#else
+    (void)nthreads;
+#endif
+}
+
+int sco_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+static double dist(const double *pos, int64_t i, int64_t j, double d[3]) {
+    d[0] = pos[3 * i + 0] - pos[3 * j + 0];
+    d[1] = pos[3 * i + 1] - pos[3 * j + 1];
+    d[2] = pos[3 * i + 2] - pos[3 * j + 2];
+    return sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+}
+
+/* A pair (i, j) contributes iff there is no cutoff or r < rc. */
+static int inside(const sco_params *p, double r) { return !(p->rc > 0.0) || r < p->rc; }
+
+/* (a/r)^k, shifted by (a/rc)^k when a cutoff is set (zero at r = rc). */
+static double power_term(const sco_params *p, double r, int k) {
+    double v = pow(p->a / r, (double)k);
+    if (p->rc > 0.0) v -= pow(p->a / p->rc, (double)k);
+    return v;
+}
+
+/* Eq. (rho): rho_i = sum_{j != i} (a / r_ij)^m. */
+void sco_density(int64_t n, const double *pos, const sco_params *p, double *rho, int nthreads) {
+    set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            double r = dist(pos, i, j, d);
+            if (!inside(p, r)) continue;
+            s += power_term(p, r, p->m);
+        }
+        rho[i] = s;
+    }
+}
+
+/*
+ * Forces F_i = -dU/dr_i of Eq. (SC).  With psi_k = rho_k^(-1/2):
+ *   F_i = eps * sum_{j != i} [ n (a/r)^n - (c m / 2)(psi_i + psi_j)(a/r)^m ] (r_i - r_j) / r^2
+ * The pair part comes from both the i and the j site terms (each holds half
+ * of the pair sum); the embedding part from d sqrt(rho_k)/d r_i for k = i
+ * and for every k = j.  Shifting by constants does not change a derivative,
+ * so the cutoff form is the same bracket restricted to r < rc, with the
+ * shifted densities inside psi.
+ *
+ * site_energy (optional) receives eps * [ 1/2 sum_j (a/r)^n - c sqrt(rho_i) ].
+ * An atom with rho_i = 0 has no neighbour; its psi is taken as 0 and is
+ * never multiplied by a non-zero term.
+ */
+void sco_forces(int64_t n, const double *pos, const sco_params *p, double *force, double *rho_out,
+                double *site_energy, int nthreads) {
+    double *rho = rho_out ? rho_out : (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *psi = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    sco_density(n, pos, p, rho, nthreads);
+    for (int64_t i = 0; i < n; ++i) psi[i] = rho[i] > 0.0 ? 1.0 / sqrt(rho[i]) : 0.0;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double f[3] = {0.0, 0.0, 0.0};
+        double pair_sum = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            double r = dist(pos, i, j, d);
+            if (!inside(p, r)) continue;
+            double an = pow(p->a / r, (double)p->n);
+            double am = pow(p->a / r, (double)p->m);
+            double coef = p->eps * ((double)p->n * an - 0.5 * p->c * (double)p->m * (psi[i] + psi[j]) * am) / (r * r);
+            f[0] += coef * d[0];
+            f[1] += coef * d[1];
+            f[2] += coef * d[2];
+            pair_sum += power_term(p, r, p->n);
+        }
+        force[3 * i + 0] = f[0];
+        force[3 * i + 1] = f[1];
+        force[3 * i + 2] = f[2];
+        if (site_energy) site_energy[i] = p->eps * (0.5 * pair_sum - p->c * sqrt(rho[i]));
+    }
+    free(psi);
+    if (!rho_out) free(rho);
+}
+
+/* Eq. (SC): U = eps * sum_i [ 1/2 sum_{j != i} (a/r)^n - c sqrt(rho_i) ]. */
+double sco_energy(int64_t n, const double *pos, const sco_params *p, double *site_energy, int nthreads) {
+    double *rho = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *site = site_energy ? site_energy : (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    sco_density(n, pos, p, rho, nthreads);
+    set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double pair_sum = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            double r = dist(pos, i, j, d);
+            if (!inside(p, r)) continue;
+            pair_sum += power_term(p, r, p->n);
+        }
+        site[i] = p->eps * (0.5 * pair_sum - p->c * sqrt(rho[i]));
+    }
+    double u = 0.0;
+    for (int64_t i = 0; i < n; ++i) u += site[i];
+    free(rho);
+    if (!site_energy) free(site);
+    return u;
+}
+
+/* Degrees of freedom of a free cluster with zero linear and angular momentum. */
+int64_t sco_ndof(int64_t n) {
+    if (n >= 3) return 3 * n - 6;
+    if (n == 2) return 1;
+    return 0;
+}
+
+double sco_kinetic(int64_t n, const double *vel, double mass_u) {
+    double s = 0.0;
+    for (int64_t i = 0; i < 3 * n; ++i) s += vel[i] * vel[i];
+    return 0.5 * mass_u * s * SCO_KE_EV_PER_U_A2_FS2;
+}
+
+double sco_temperature(int64_t n, const double *vel, double mass_u) {
+    int64_t dof = sco_ndof(n);
+    if (dof <= 0) return 0.0;
+    return 2.0 * sco_kinetic(n, vel, mass_u) / ((double)dof * SCO_KB_EV_PER_K);
+}
+
+/* Linear target ramp: T_s + (T_e - T_s) * min(k, K) / K (K <= 0: T_e at once). */
+double sco_target_temperature(const sco_thermostat *t, int64_t k) {
+    if (t->ramp_steps <= 0) return t->T_end;
+    int64_t kk = k < t->ramp_steps ? k : t->ramp_steps;
+    return t->T_start + (t->T_end - t->T_start) * (double)kk / (double)t->ramp_steps;
+}
+
+/* Berendsen factor lambda = sqrt(1 + (dt/tau)(T_target/T - 1)); 1 when T = 0. */
+double sco_berendsen_lambda(double T, double T_target, double dt, double tau) {
+    if (!(T > 0.0)) return 1.0;
+    double x = 1.0 + (dt / tau) * (T_target / T - 1.0);
+    return x > 0.0 ? sqrt(x) : 0.0;
+}
+
+/*
+ * Velocity-Verlet trajectory.  On entry pos/vel hold r(t0), v(t0) (n x 3,
+ * row-major); force holds F(r(t0)) when have_force is set, else it is
+ * computed first.  Each step:
+ *   v += (dt/2m) F;  r += dt v;  F = F(r);  v += (dt/2m) F;
+ *   then, for the Berendsen kind, T from v, the target of the completed
+ *   step index (step0 + k), and v *= lambda.
+ * Per step k (0-based in this call) the log receives, when not NULL,
+ *   log[4k + 0] = E_pot, [1] = E_kin, [2] = T, [3] = T_target,
+ * all of the state after the thermostat has acted.
+ */
+int sco_vv_run(int64_t n, double *pos, double *vel, double *force, int have_force, const sco_params *p,
+               double mass_u, double dt, int64_t nsteps, const sco_thermostat *thermo, int64_t step0,
+               double *log, int nthreads) {
+    if (n < 0 || nsteps < 0 || !(dt > 0.0) || !(mass_u > 0.0)) return -1;
+    double h = 0.5 * dt / (mass_u * SCO_KE_EV_PER_U_A2_FS2);
+    double *site = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!have_force) sco_forces(n, pos, p, force, NULL, NULL, nthreads);
+    for (int64_t k = 0; k < nsteps; ++k) {
+        for (int64_t i = 0; i < 3 * n; ++i) vel[i] += h * force[i];
+        for (int64_t i = 0; i < 3 * n; ++i) pos[i] += dt * vel[i];
+        sco_forces(n, pos, p, force, NULL, site, nthreads);
+        for (int64_t i = 0; i < 3 * n; ++i) vel[i] += h * force[i];
+        double T = sco_temperature(n, vel, mass_u);
+        double Tt = 0.0;
+        if (thermo && thermo->kind == SCO_BERENDSEN) {
+            Tt = sco_target_temperature(thermo, step0 + k + 1);
+            double lam = sco_berendsen_lambda(T, Tt, dt, thermo->tau);
+            for (int64_t i = 0; i < 3 * n; ++i) vel[i] *= lam;
+            T = sco_temperature(n, vel, mass_u);
+        }
+        if (log) {
+            double u = 0.0;
+            for (int64_t i = 0; i < n; ++i) u += site[i];
+            log[4 * k + 0] = u;
+            log[4 * k + 1] = sco_kinetic(n, vel, mass_u);
+            log[4 * k + 2] = T;
+            log[4 * k + 3] = Tt;
+        }
+    }
+    free(site);
+    return 0;
+}

@@ -1,0 +1,90 @@
+"""The pins are sharp: plant plausible mistakes in a copy of the oracle source
+(a dropped factor, a swapped index, a wrong sign or exponent, a wrong
+integrator or thermostat constant), build the copy on the CPU and check that
+at least one pin of ``test_oracle_pins`` fails for every mutant."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+from paper_1210_3559_amd import inputs
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "sc_oracle.c")
+
+MUTANTS = {
+    "psi_index": ("(psi[i] + psi[j])", "(psi[i] + psi[i])"),
+    "pair_half_dropped": ("0.5 * pair_sum", "pair_sum"),
+    "embedding_half_dropped": ("0.5 * p->c * (double)p->m", "p->c * (double)p->m"),
+    "dy_transposed": ("pos[3 * i + 1] - pos[3 * j + 1]", "pos[3 * j + 1] - pos[3 * i + 1]"),
+    "inverse_r_not_squared": ("/ (r * r)", "/ r"),
+    "repulsive_exponent": ("double an = pow(p->a / r, (double)p->n);", "double an = pow(p->a / r, (double)p->m);"),
+    "embedding_sign": ("- p->c * sqrt(rho[i])", "+ p->c * sqrt(rho[i])"),
+    "full_kick": ("double h = 0.5 * dt /", "double h = dt /"),
+    "ndof": ("return 3 * n - 6;", "return 3 * n;"),
+    "berendsen_ratio": ("(T_target / T - 1.0)", "(T / T_target - 1.0)"),
+    "shift_sign": ("if (p->rc > 0.0) v -= pow(", "if (p->rc > 0.0) v += pow("),
+    "ke_half": ("return 0.5 * mass_u * s *", "return mass_u * s *"),
+    "ramp_index": ("t->T_start + (t->T_end - t->T_start) * (double)kk", "t->T_end + (t->T_start - t->T_end) * (double)kk"),
+}
+
+
+def _build(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert old in src, f"mutation anchor for {name} not found"
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    hdr = os.path.join(os.path.dirname(SRC), "sc_oracle.h")
+    lib = tmp_path / f"lib_{name}.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                    "-I", os.path.dirname(hdr), str(path), "-o", str(lib), "-lm"], check=True)
+    return oracle.load_variant(str(lib))
+
+
+def _pin_calls():
+    ball = (inputs.fcc_sphere(24.0, pins.A), 24.0)
+    ni147 = (inputs.c1_icosahedron().pos, inputs.c1_icosahedron().vel)
+    calls = [
+        lambda o: pins.test_parameter_set_is_the_papers(o),
+        lambda o: pins.test_dimer_closed_form(o, 2.49),
+        lambda o: pins.test_dimer_equilibrium(o),
+        lambda o: pins.test_equilateral_trimer(o),
+        lambda o: pins.test_central_density_matches_fcc_lattice_sum(o, ball),
+        lambda o: pins.test_central_site_energy_is_ni_cohesive_energy(o, ball),
+        lambda o: pins.test_forces_are_minus_energy_gradient(o, None),
+        lambda o: pins.test_forces_are_minus_energy_gradient(o, dict(rc=8.8)),
+        lambda o: pins.test_net_force_and_torque_vanish(o),
+        lambda o: pins.test_translation_rotation_permutation_scaling(o),
+        lambda o: pins.test_mackay_icosahedron_symmetry(o),
+        lambda o: pins.test_cutoff_dimer_and_limits(o),
+        lambda o: pins.test_ndof_rule(o),
+        lambda o: pins.test_maxwell_boltzmann_sample_has_its_temperature(o),
+        lambda o: pins.test_berendsen_ramp_target(o),
+        lambda o: pins.test_dimer_harmonic_period(o),
+        lambda o: pins.test_berendsen_relaxes_to_target(o, ni147),
+        lambda o: pins.test_time_reversibility(o, ni147),
+    ]
+    return calls
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(tmp_path, name):
+    old, new = MUTANTS[name]
+    mutant = _build(tmp_path, name, old, new)
+    caught = None
+    with np.errstate(all="ignore"):
+        for i, call in enumerate(_pin_calls()):
+            try:
+                call(mutant)
+            except (AssertionError, ValueError, FloatingPointError):
+                caught = i
+                break
+    assert caught is not None, f"no pin caught mutant {name}"
+
+
+def test_unmutated_copy_passes_every_pin(tmp_path):
+    clean = _build(tmp_path, "clean", "#include <math.h>", "#include <math.h>")
+    for call in _pin_calls():
+        call(clean)
