@@ -1,0 +1,237 @@
+/*
+ * scmd.h -- C ABI of an MI355X (gfx950) molecular-dynamics library for free
+ * nickel clusters with the Sutton-Chen many-body potential.
+ *
+ * What the library computes (Yakubovich, Sushko, Schramm, Solov'yov,
+ * "Kinetics of liquid-solid phase transition in large nickel clusters",
+ * arXiv:1210.3559):
+ *   - potential energy U = eps sum_i [ 1/2 sum_{j!=i} (a/r_ij)^n - c sqrt(rho_i) ]
+ *     (Sec. 2.1, Eq. (SC)) with rho_i = sum_{j!=i} (a/r_ij)^m (Eq. (rho));
+ *   - the forces -grad U, evaluated as two all-pairs sweeps: first every
+ *     rho_i, then the forces (Sec. 2, "Computational approach");
+ *   - Verlet time stepping, read as velocity-Verlet (same section, last
+ *     paragraph), with an optional Berendsen thermostat following a linear
+ *     temperature ramp (the cooling runs of the paper's workloads are driven
+ *     this way here; the paper's own Langevin thermostat is not provided);
+ *   - optionally the potential truncated at rc with both power sums shifted
+ *     to zero there (not in the paper, which calls a cutoff future work),
+ *     evaluated with a cell list.
+ *
+ * Several independent clusters ("a batch") can live in one context; they
+ * are stored back to back (CSR offsets) and advanced together.
+ *
+ * Units: Angstrom, fs, eV, atomic mass unit u, Kelvin.
+ * Host arrays of positions, velocities and forces are n x 3 row-major double
+ * (x y z per atom, atoms in the order given at init).
+ *
+ * Errors: every call returns SCMD_OK (0) or a negative SCMD_E* code; on
+ * error no output argument is written and scmd_last_error() describes the
+ * failure.  No C++ exception crosses this interface.
+ *
+ * Ownership: the caller owns every buffer it passes; the library copies
+ * inputs during the call and never keeps a caller pointer.  The library
+ * owns its device memory and graph objects; scmd_destroy releases them.
+ *
+ * Threading and streams: a context is not thread-safe.  All device work of
+ * a context is ordered on one HIP stream (the one given to scmd_create, or
+ * a non-blocking stream the library creates).
+ *
+ * Call order: scmd_create -> scmd_init_clusters -> scmd_set_potential ->
+ * scmd_set_integrator -> [scmd_set_thermostat ...] -> scmd_compute /
+ * scmd_step -> scmd_get_*.  A call before its prerequisites returns
+ * SCMD_ESTATE.  Re-initialising clusters or changing the potential or the
+ * integrator discards the step count, forces and captured graphs.
+ */
+#ifndef SCMD_H
+#define SCMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SCMD_ABI_VERSION 1
+
+typedef struct scmd_ctx scmd_ctx;
+
+/* Status codes. */
+enum {
+    SCMD_OK = 0,
+    SCMD_EINVAL = -1,       /* bad argument (null pointer, size, range)            */
+    SCMD_ENOMEM = -2,       /* device or host allocation failed                     */
+    SCMD_EDEVICE = -3,      /* no usable gfx950 device or a HIP runtime error       */
+    SCMD_ENONFINITE = -4,   /* a non-finite energy appeared (e.g. coincident atoms) */
+    SCMD_ESTATE = -5,       /* call out of order                                    */
+    SCMD_EBOX = -6,         /* cell grid would exceed its cap (atom escaped far)    */
+    SCMD_EUNSUPPORTED = -7  /* valid request this build does not implement          */
+};
+
+/* Arithmetic of the pair sweeps. */
+enum {
+    SCMD_FP64 = 0,  /* every operation in double precision                          */
+    SCMD_MIXED = 1  /* r_i - r_j in double, then r^2, powers and the pair
+                       coefficient in single precision; each term added to double
+                       accumulators; positions, velocities and integration double */
+};
+
+/* Neighbour handling. */
+enum {
+    SCMD_ALLPAIRS = 0, /* every pair (i, j != i); requires rc == 0                 */
+    SCMD_CELLLIST = 1  /* pairs with r < rc found through a cell list; rc > 0      */
+};
+
+/* Thermostats. */
+enum {
+    SCMD_NVE = 0,       /* no thermostat                                             */
+    SCMD_BERENDSEN = 1, /* velocity rescaling towards a linear ramp T_start -> T_end */
+    SCMD_LANGEVIN = 2   /* the paper's thermostat; not provided (SCMD_EUNSUPPORTED)  */
+};
+
+/* Sutton-Chen parameters (Sec. 2.1).  Ni: eps = 1.5707e-2 eV, a = 3.52 A,
+ * c = 39.432, n = 9, m = 6.  Integer exponents with 1 <= m < n <= 24.
+ * rc > 0 truncates at rc and shifts (a/r)^n and (a/r)^m to zero there. */
+typedef struct {
+    double eps;
+    double a;
+    double c;
+    int n;
+    int m;
+    double rc;
+} scmd_sc_params;
+
+/* Launch shape of the pair sweeps (all zero = library defaults).
+ * block: threads per workgroup (64, 128 or 256); ipt: atoms owned per thread
+ * (1, 2 or 4); target_items: aim for about this many workgroups per sweep when
+ * splitting the j range of each atom tile (0 = default). */
+typedef struct {
+    int block;
+    int ipt;
+    int target_items;
+    int reserved;
+} scmd_tuning;
+
+/* Kernel classes timed by scmd_get_kernel_time (device time per launch). */
+enum {
+    SCMD_KERNEL_DENSITY = 0, /* density sweep (rho partial sums)          */
+    SCMD_KERNEL_FORCE = 1,   /* force sweep (force and pair-energy sums)   */
+    SCMD_KERNEL_COUNT = 2
+};
+
+/* Returns SCMD_ABI_VERSION. */
+int scmd_abi_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char *scmd_status_string(int status);
+
+/* Create a context on HIP device `device` (must be gfx950).  `hip_stream`
+ * is a hipStream_t the caller keeps alive for the context's lifetime, or NULL
+ * for a library-owned non-blocking stream.  *out receives the context.
+ * Returns SCMD_EDEVICE when there is no such device. */
+int scmd_create(scmd_ctx **out, int device, void *hip_stream);
+
+/* Wait for outstanding work and free everything the context owns.  NULL is
+ * accepted and ignored. */
+int scmd_destroy(scmd_ctx *ctx);
+
+/* Load n_clusters independent clusters.  offsets[n_clusters + 1] (host,
+ * int64, offsets[0] = 0, non-decreasing; empty clusters allowed) delimit the
+ * atoms of each cluster inside pos and vel (host, offsets[n_clusters] x 3
+ * doubles, A and A/fs).  vel may be NULL (all zero).  mass_u > 0 is the atomic
+ * mass (58.6934 for Ni).  The total atom count must be below 2^30.  Copies the
+ * data to the device; the caller's arrays may be reused at return. */
+int scmd_init_clusters(scmd_ctx *ctx, int n_clusters, const int64_t *offsets, const double *pos,
+                       const double *vel, double mass_u);
+
+/* Set the potential (Sec. 2.1).  Requires eps > 0, a > 0, c >= 0,
+ * 1 <= m < n <= 24 and rc >= 0. */
+int scmd_set_potential(scmd_ctx *ctx, const scmd_sc_params *params);
+
+/* Time step dt_fs > 0 (the paper uses 1 fs), precision SCMD_FP64 or
+ * SCMD_MIXED, neighbour SCMD_ALLPAIRS (needs rc == 0) or SCMD_CELLLIST
+ * (needs rc > 0). */
+int scmd_set_integrator(scmd_ctx *ctx, double dt_fs, int precision, int neighbour);
+
+/* Thermostat of one cluster (cluster = -1: every cluster).  Berendsen: after
+ * the second half-kick of step k (k counts completed steps of that cluster
+ * since init, from 1), T_k = 2 E_kin / (ndof k_B) with ndof = 3N - 6 (1 for a
+ * dimer, 0 below), target T_start + (T_end - T_start) min(k, K)/K
+ * (K = ramp_steps; K <= 0 means T_end at once), lambda =
+ * sqrt(1 + (dt/tau)(target/T_k - 1)) (1 when T_k = 0, 0 when the radicand is
+ * negative), v <- lambda v.  tau_fs > 0; temperatures >= 0.  SCMD_NVE
+ * ignores the other arguments.  SCMD_LANGEVIN returns SCMD_EUNSUPPORTED. */
+int scmd_set_thermostat(scmd_ctx *ctx, int cluster, int kind, double T_start_K, double T_end_K,
+                        int64_t ramp_steps, double tau_fs);
+
+/* Override the sweep launch shape (NULL restores defaults). */
+int scmd_set_tuning(scmd_ctx *ctx, const scmd_tuning *tuning);
+
+/* Evaluate rho, forces, energies and temperature at the current positions,
+ * without moving atoms.  Enqueued on the context stream; synchronises and
+ * returns SCMD_ENONFINITE when an energy is not finite. */
+int scmd_compute(scmd_ctx *ctx);
+
+/* Advance every cluster by nsteps >= 0 velocity-Verlet steps (forces at the
+ * initial positions are computed first if needed).  Steps are replayed from
+ * captured HIP graphs.  Waits for completion and returns SCMD_ENONFINITE
+ * if an energy became non-finite during these steps (the state is then
+ * undefined). */
+int scmd_step(scmd_ctx *ctx, int64_t nsteps);
+
+/* As scmd_step, but only enqueues the work: returns without waiting; errors
+ * from the device surface at the next scmd_synchronize or getter. */
+int scmd_step_async(scmd_ctx *ctx, int64_t nsteps);
+
+/* Wait for the context stream; returns SCMD_ENONFINITE if flagged. */
+int scmd_synchronize(scmd_ctx *ctx);
+
+/* Completed steps of the context (all clusters advance together). */
+int scmd_get_step(scmd_ctx *ctx, int64_t *step);
+
+/* Energies of the current state of one cluster (cluster = -1: sum over all):
+ * out3[0] = E_pot, out3[1] = E_kin, out3[2] = E_pot + E_kin, eV.  Valid after
+ * scmd_compute or scmd_step. */
+int scmd_get_energy(scmd_ctx *ctx, int cluster, double out3[3]);
+
+/* Temperature (K) and degrees of freedom of one cluster's current state. */
+int scmd_get_temperature(scmd_ctx *ctx, int cluster, double *T_K, int64_t *ndof);
+
+/* Copy current state to host arrays of offsets[n_clusters] x 3 doubles
+ * (density: offsets[n_clusters] doubles).  Velocities include any pending
+ * thermostat factor.  Forces and density are those of the current positions
+ * (valid after scmd_compute or scmd_step). */
+int scmd_get_positions(scmd_ctx *ctx, double *out);
+int scmd_get_velocities(scmd_ctx *ctx, double *out);
+int scmd_get_forces(scmd_ctx *ctx, double *out);
+int scmd_get_density(scmd_ctx *ctx, double *out);
+
+/* Device variant: write the forces (n x 3 doubles, row-major) into caller
+ * device memory dev_out, ordered on the context stream; does not wait. */
+int scmd_get_forces_device(scmd_ctx *ctx, double *dev_out);
+
+/* Checkpoint: scmd_get_state writes a self-describing blob (positions,
+ * velocities, forces, thermostat factors and settings, step counts) into buf
+ * of *bytes capacity; with buf NULL it only stores the needed size in *bytes.
+ * scmd_set_state restores a blob taken from a context with the same cluster
+ * layout; stepping on from it reproduces the uninterrupted run bit for bit. */
+int scmd_get_state(scmd_ctx *ctx, void *buf, size_t *bytes);
+int scmd_set_state(scmd_ctx *ctx, const void *buf, size_t bytes);
+
+/* Record device time per launch of the pair sweeps during subsequent
+ * scmd_step / scmd_compute calls (HIP events around each launch on the context
+ * stream, also inside captured graphs).  enable = 0 stops recording. */
+int scmd_set_profiling(scmd_ctx *ctx, int enable);
+
+/* Average device milliseconds per launch of a kernel class over the launches
+ * recorded since profiling was enabled, and how many launches that covers. */
+int scmd_get_kernel_time(scmd_ctx *ctx, int kernel, double *avg_ms, int64_t *launches);
+
+/* Last error message of this context (or of the last failed scmd_create when
+ * ctx is NULL).  The string stays valid until the next call on the context. */
+const char *scmd_last_error(const scmd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCMD_H */

@@ -71,6 +71,8 @@ def _configure(lib):
     lib.sco_density.restype = None
     lib.sco_forces.argtypes = [i64, vp, pp, vp, vp, vp, ctypes.c_int]
     lib.sco_forces.restype = None
+    lib.sco_forces_subset.argtypes = [i64, vp, pp, vp, i64, vp, vp, ctypes.c_int]
+    lib.sco_forces_subset.restype = None
     lib.sco_energy.argtypes = [i64, vp, pp, vp, ctypes.c_int]
     lib.sco_energy.restype = dbl
     lib.sco_ndof.argtypes = [i64]
@@ -156,6 +158,19 @@ def forces(pos, params=None, nthreads: int = 1):
     return f, rho, site
 
 
+def forces_subset(pos, idx, params=None, nthreads: int = 1):
+    """Forces of the listed atoms only (k x 3) and the full density (n,)."""
+    r = _pos(pos)
+    ix = np.ascontiguousarray(idx, dtype=np.int64)
+    if ix.size and (ix.min() < 0 or ix.max() >= len(r)):
+        raise ValueError("atom index out of range")
+    f = np.zeros((len(ix), 3))
+    rho = np.zeros(len(r))
+    p = _params(params)
+    _load().sco_forces_subset(len(r), _ptr(r), ctypes.byref(p), _ptr(ix), len(ix), _ptr(f), _ptr(rho), nthreads)
+    return f, rho
+
+
 def energy(pos, params=None, nthreads: int = 1) -> float:
     """Eq. (SC): total potential energy, eV."""
     r = _pos(pos)
@@ -228,7 +243,7 @@ def load_variant(lib_path: str):
     lib = _configure(ctypes.CDLL(lib_path))
     ns = types.SimpleNamespace(NI_PARAMS=NI_PARAMS, NI_MASS_U=NI_MASS_U)
     g = globals()
-    for name in ("max_threads", "ke_conversion", "kb", "density", "forces", "energy", "site_energies", "ndof",
+    for name in ("max_threads", "ke_conversion", "kb", "density", "forces", "forces_subset", "energy", "site_energies", "ndof",
                  "kinetic", "temperature", "target_temperature", "berendsen_lambda", "vv_run"):
         fn = g[name]
         def bound(*a, _fn=fn, **k):

@@ -143,6 +143,42 @@ void sco_forces(int64_t n, const double *pos, const sco_params *p, double *force
     if (!rho_out) free(rho);
 }
 
+/*
+ * The same force definition evaluated only for the k atoms listed in idx
+ * (for spot checks of large systems): the density sweep still covers every
+ * atom, because F_i needs psi_j of every partner j.  force receives k x 3.
+ */
+void sco_forces_subset(int64_t n, const double *pos, const sco_params *p, const int64_t *idx, int64_t k,
+                       double *force, double *rho_out, int nthreads) {
+    double *rho = rho_out ? rho_out : (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *psi = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    sco_density(n, pos, p, rho, nthreads);
+    for (int64_t i = 0; i < n; ++i) psi[i] = rho[i] > 0.0 ? 1.0 / sqrt(rho[i]) : 0.0;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < k; ++q) {
+        const int64_t i = idx[q];
+        double f[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            double r = dist(pos, i, j, d);
+            if (!inside(p, r)) continue;
+            double an = pow(p->a / r, (double)p->n);
+            double am = pow(p->a / r, (double)p->m);
+            double coef = p->eps * ((double)p->n * an - 0.5 * p->c * (double)p->m * (psi[i] + psi[j]) * am) / (r * r);
+            f[0] += coef * d[0];
+            f[1] += coef * d[1];
+            f[2] += coef * d[2];
+        }
+        force[3 * q + 0] = f[0];
+        force[3 * q + 1] = f[1];
+        force[3 * q + 2] = f[2];
+    }
+    free(psi);
+    if (!rho_out) free(rho);
+}
+
 /* Eq. (SC): U = eps * sum_i [ 1/2 sum_{j != i} (a/r)^n - c sqrt(rho_i) ]. */
 double sco_energy(int64_t n, const double *pos, const sco_params *p, double *site_energy, int nthreads) {
     double *rho = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));

@@ -42,6 +42,8 @@ int sco_max_threads(void);
 void sco_density(int64_t n, const double *pos, const sco_params *p, double *rho, int nthreads);
 void sco_forces(int64_t n, const double *pos, const sco_params *p, double *force, double *rho_out,
                 double *site_energy, int nthreads);
+void sco_forces_subset(int64_t n, const double *pos, const sco_params *p, const int64_t *idx, int64_t k,
+                       double *force, double *rho_out, int nthreads);
 double sco_energy(int64_t n, const double *pos, const sco_params *p, double *site_energy, int nthreads);
 
 int64_t sco_ndof(int64_t n);

@@ -1,0 +1,105 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// the Sutton-Chen cluster-MD library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scmd {
+
+// 1 u*A^2/fs^2 in eV (CODATA 2018 e and u) and k_B in eV/K.
+constexpr double kEvPerUA2Fs2 = 103.64269652680505;
+constexpr double kBoltzmannEv = 8.617333262145179e-05;
+
+// Sentinel coordinates for lanes/atoms past the end of a tile.  Atom slots
+// past the owned range sit at -kFar, j slots past a chunk at +kFar, so every
+// pair touching a sentinel has r^2 ~ 1e301: all its power terms underflow to
+// exactly zero in double precision (and to inf -> 0 through rsqrt/rcp in
+// single precision), and no sentinel ever meets another at r = 0.
+constexpr double kFar = 1.0e150;
+
+// Sutton-Chen constants folded for the kernels.  With u = 1/r:
+//   rho_i      = a^m sum_j u^m                      (density sweep)
+//   F_i        = sum_j u^(m+2) [A u^(n-m) - P_i - P_j] (r_i - r_j)
+//                with A = eps n a^n and P_k = eps (c m / 2) a^m psi_k,
+//   E_pair_i   = (eps/2) a^n sum_j u^n,  E_emb_i = -eps c sqrt(rho_i).
+// Cutoff variant: shifted powers (a/r)^k - (a/rc)^k for r < rc.
+struct PotConst {
+    double am;        // a^m
+    double A;         // eps * n * a^n
+    double Pscale;    // eps * c * m / 2 * a^m   (P_k = Pscale * psi_k)
+    double half_eps_an;  // eps/2 * a^n
+    double eps_c;     // eps * c
+    double rc2;       // rc^2 (0: all pairs)
+    double inv_rc_m;  // rc^-m  (shift of u^m)
+    double inv_rc_n;  // rc^-n  (shift of u^n)
+    int n, m;
+    int cut;          // 1 when rc > 0
+    int generic;      // 1 unless (n, m) == (9, 6)
+};
+
+// One cluster of a batch (device table).
+struct ClusterDesc {
+    int32_t off;        // first atom
+    int32_t n;          // atoms
+    int32_t tile0;      // first atom tile
+    int32_t ntiles;     // atom tiles
+    int64_t ndof;
+    int32_t kind;       // thermostat kind
+    int32_t pad;
+    double T_start, T_end, tau;
+    int64_t ramp;
+};
+
+// Mutable per-cluster state (device).
+struct ClusterState {
+    double lambda;      // thermostat factor not yet applied to the velocities
+    double epot, ekin, temp, ttarget;
+    int64_t step;       // completed steps
+    int32_t nonfinite;
+    int32_t pad;
+};
+
+// A pair-sweep work item: atoms [i0, i0+ni) against j in [j0, j1), partial
+// sums written to slot `slot`.
+struct SweepItem {
+    int32_t c, i0, ni, j0, j1, slot;
+};
+
+// An atom tile: atoms [i0, i0+ni) of cluster c whose partial sums sit in
+// slots [first, first+nsplit).
+struct ITile {
+    int32_t c, i0, ni, first, nsplit, pad;
+};
+
+// Launch helpers implemented in the .hip files.
+struct SweepLaunch {
+    const SweepItem *items;
+    const int32_t *order;
+    int nitems;
+    int block;   // threads per workgroup
+    int ipt;     // atoms per thread
+    int tile;    // block * ipt
+};
+
+hipError_t launch_density(const SweepLaunch &L, const double4 *rp, double *part, const PotConst &pc,
+                          int precision, hipStream_t s);
+hipError_t launch_force(const SweepLaunch &L, const double4 *rp, double *part, const PotConst &pc,
+                        int precision, hipStream_t s);
+
+hipError_t launch_drift(const int32_t *atom_cluster, const ClusterState *st, double4 *rp, double4 *v,
+                        const double4 *f, int natoms, double dt, double h, hipStream_t s);
+hipError_t launch_density_reduce(const ITile *tiles, int ntiles, int tile, const double *part, double4 *rp,
+                                 double *rho, double *tile_sums, const PotConst &pc, hipStream_t s);
+hipError_t launch_force_reduce(const ITile *tiles, int ntiles, int tile, const double *part, double4 *f,
+                               double4 *v, double *tile_sums, const PotConst &pc, double h, int kick,
+                               hipStream_t s);
+hipError_t launch_finalize(const ClusterDesc *cd, ClusterState *st, int nclusters, const double *tile_sums,
+                           double mass_u, double dt, int advance, int *flag, hipStream_t s);
+hipError_t launch_aos_from4(const double4 *src, double *dst, int natoms, hipStream_t s);
+
+// Number of doubles per tile in tile_sums: [0] sum e_emb, [1] sum e_pair,
+// [2] sum v^2.
+constexpr int kTileSums = 4;
+
+}  // namespace scmd

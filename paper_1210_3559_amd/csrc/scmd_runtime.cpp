@@ -1,0 +1,1054 @@
+// Host runtime of the Sutton-Chen cluster-MD library: the C ABI declared in
+// include/scmd.h.  It validates arguments, owns device memory, plans the
+// split of the all-pairs sweeps into work items, enqueues the per-step kernel
+// sequence on the context stream and replays it from captured HIP graphs.
+#include "../../include/scmd.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cell_list.h"
+#include "scmd_internal.h"
+
+using namespace scmd;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr int kGraphSteps = 32;  // steps per captured graph
+
+struct EvPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    int kind = 0;
+};
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t ensure(size_t count) {
+        if (count <= n && p) return hipSuccess;
+        release();
+        if (count == 0) return hipSuccess;
+        hipError_t e = hipMalloc((void **)&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        n = count;
+        return hipSuccess;
+    }
+};
+
+}  // namespace
+
+struct scmd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;
+    std::string err;
+
+    // configuration
+    bool have_clusters = false, have_pot = false, have_integ = false;
+    int nclusters = 0;
+    int natoms = 0;
+    double mass = 0.0;
+    std::vector<int64_t> offsets;
+    std::vector<ClusterDesc> cdesc;
+    scmd_sc_params params{};
+    PotConst pc{};
+    double dt = 0.0;
+    int precision = SCMD_FP64;
+    int neighbour = SCMD_ALLPAIRS;
+    scmd_tuning tuning{};
+
+    // device state
+    DevBuf<double4> rp, v, f;
+    DevBuf<double> rho;
+    DevBuf<int32_t> atom_cluster;
+    DevBuf<ClusterDesc> d_cdesc;
+    DevBuf<ClusterState> d_state;
+    DevBuf<int> d_flag;
+    int *h_flag = nullptr;  // pinned
+
+    // all-pairs plan
+    bool plan_ok = false;
+    int block = 256, ipt = 1, tile = 256;
+    int nitems = 0, ntiles = 0;
+    DevBuf<SweepItem> d_items;
+    DevBuf<int32_t> d_order;
+    DevBuf<ITile> d_tiles;
+    DevBuf<double> d_part;
+    DevBuf<double> d_tile_sums;
+
+    // cell-list plan (cutoff variant)
+    CellList *cells = nullptr;
+
+    // progress
+    bool have_forces = false;
+    int64_t step = 0;
+
+    // graphs
+    hipGraphExec_t graph = nullptr;
+    int graph_profiled = 0;
+
+    // profiling
+    int profiling = 0;
+    bool graph_events_ok = true;
+    std::vector<EvPair> evs;
+    std::vector<int> ev_free, ev_pending, ev_graph;
+    bool graph_unread = false;
+    double prof_ms[SCMD_KERNEL_COUNT] = {0, 0};
+    int64_t prof_n[SCMD_KERNEL_COUNT] = {0, 0};
+};
+
+namespace {
+
+int fail(scmd_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                                  \
+    do {                                                                                                    \
+        hipError_t e_ = (expr);                                                                             \
+        if (e_ != hipSuccess)                                                                               \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? SCMD_ENOMEM : SCMD_EDEVICE,                      \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                                 \
+    } while (0)
+
+#define SCMD_GUARD(...)                                          \
+    try {                                                        \
+        __VA_ARGS__                                              \
+    } catch (const std::bad_alloc &) {                           \
+        return fail(ctx, SCMD_ENOMEM, "host allocation failed"); \
+    } catch (...) {                                              \
+        return fail(ctx, SCMD_EDEVICE, "internal error");        \
+    }
+
+int64_t ndof_of(int64_t n) {
+    if (n >= 3) return 3 * n - 6;
+    if (n == 2) return 1;
+    return 0;
+}
+
+PotConst make_pot(const scmd_sc_params &p) {
+    PotConst pc{};
+    pc.n = p.n;
+    pc.m = p.m;
+    pc.am = std::pow(p.a, (double)p.m);
+    const double an = std::pow(p.a, (double)p.n);
+    pc.A = p.eps * (double)p.n * an;
+    pc.Pscale = p.eps * p.c * (double)p.m * 0.5 * pc.am;
+    pc.half_eps_an = 0.5 * p.eps * an;
+    pc.eps_c = p.eps * p.c;
+    pc.cut = p.rc > 0.0 ? 1 : 0;
+    pc.rc2 = p.rc * p.rc;
+    pc.inv_rc_m = p.rc > 0.0 ? std::pow(p.rc, -(double)p.m) : 0.0;
+    pc.inv_rc_n = p.rc > 0.0 ? std::pow(p.rc, -(double)p.n) : 0.0;
+    pc.generic = (p.n == 9 && p.m == 6) ? 0 : 1;
+    return pc;
+}
+
+void drop_graph(scmd_ctx *c) {
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    for (int i : c->ev_graph) c->ev_free.push_back(i);
+    c->ev_graph.clear();
+    c->graph_unread = false;
+}
+
+bool ready(scmd_ctx *c) { return c->have_clusters && c->have_pot && c->have_integ; }
+
+// -------------------------------------------------------------------------
+// Profiling events
+// -------------------------------------------------------------------------
+int take_event(scmd_ctx *c, int kind) {
+    int idx;
+    if (!c->ev_free.empty()) {
+        idx = c->ev_free.back();
+        c->ev_free.pop_back();
+    } else {
+        EvPair e;
+        if (hipEventCreate(&e.a) != hipSuccess) return -1;
+        if (hipEventCreate(&e.b) != hipSuccess) {
+            (void)hipEventDestroy(e.a);
+            return -1;
+        }
+        c->evs.push_back(e);
+        idx = (int)c->evs.size() - 1;
+    }
+    c->evs[idx].kind = kind;
+    return idx;
+}
+
+void harvest_events(scmd_ctx *c) {
+    auto read = [&](int idx) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->evs[idx].a, c->evs[idx].b) == hipSuccess) {
+            c->prof_ms[c->evs[idx].kind] += ms;
+            c->prof_n[c->evs[idx].kind] += 1;
+        }
+    };
+    for (int idx : c->ev_pending) {
+        read(idx);
+        c->ev_free.push_back(idx);
+    }
+    c->ev_pending.clear();
+    if (c->graph_unread) {
+        for (int idx : c->ev_graph) read(idx);
+        c->graph_unread = false;
+    }
+}
+
+// -------------------------------------------------------------------------
+// Plan: atom tiles and sweep items
+// -------------------------------------------------------------------------
+int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
+    c->plan_ok = false;
+    c->block = c->tuning.block > 0 ? c->tuning.block : 256;
+    c->ipt = c->tuning.ipt > 0 ? c->tuning.ipt : 1;
+    if (c->pc.generic) {
+        c->block = 256;
+        c->ipt = 1;
+    }
+    c->tile = c->block * c->ipt;
+    const int target = c->tuning.target_items > 0 ? c->tuning.target_items : 2048;
+    const int tile = c->tile;
+    std::vector<ITile> tiles;
+    std::vector<SweepItem> items;
+    double total = 0.0;
+    for (int k = 0; k < c->nclusters; ++k) {
+        const int64_t n = c->offsets[k + 1] - c->offsets[k];
+        const int64_t nt = (n + tile - 1) / tile;
+        total += (double)nt * tile * (double)n;
+    }
+    const double wstar = std::max(total / target, (double)tile * 64.0);
+    for (int k = 0; k < c->nclusters; ++k) {
+        ClusterDesc &d = c->cdesc[k];
+        const int off = (int)c->offsets[k];
+        const int n = (int)(c->offsets[k + 1] - c->offsets[k]);
+        d.off = off;
+        d.n = n;
+        d.tile0 = (int)tiles.size();
+        d.ntiles = (n + tile - 1) / tile;
+        d.ndof = ndof_of(n);
+        int nsplit = (int)std::ceil((double)tile * (double)n / wstar);
+        nsplit = std::max(1, std::min(nsplit, std::max(1, n / 64)));
+        if (c->neighbour == SCMD_CELLLIST) nsplit = 1;  // cell sweeps write complete sums
+        for (int t = 0; t < d.ntiles; ++t) {
+            ITile T{};
+            T.c = k;
+            T.i0 = off + t * tile;
+            T.ni = std::min(tile, n - t * tile);
+            T.first = (int)items.size();
+            T.nsplit = nsplit;
+            for (int s = 0; s < nsplit; ++s) {
+                SweepItem it{};
+                it.c = k;
+                it.i0 = T.i0;
+                it.ni = T.ni;
+                it.j0 = off + (int)((int64_t)n * s / nsplit);
+                it.j1 = off + (int)((int64_t)n * (s + 1) / nsplit);
+                it.slot = (int)items.size();
+                items.push_back(it);
+            }
+            tiles.push_back(T);
+        }
+    }
+    std::vector<int32_t> order(items.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        const int64_t wx = (int64_t)items[x].ni * (items[x].j1 - items[x].j0);
+        const int64_t wy = (int64_t)items[y].ni * (items[y].j1 - items[y].j0);
+        return wx > wy;
+    });
+    c->nitems = (int)items.size();
+    c->ntiles = (int)tiles.size();
+    HIP_TRY(c, c->d_items.ensure(std::max<size_t>(items.size(), 1)));
+    HIP_TRY(c, c->d_order.ensure(std::max<size_t>(order.size(), 1)));
+    HIP_TRY(c, c->d_tiles.ensure(std::max<size_t>(tiles.size(), 1)));
+    HIP_TRY(c, c->d_part.ensure(std::max<size_t>((size_t)items.size() * 4 * tile, 1)));
+    HIP_TRY(c, c->d_tile_sums.ensure(std::max<size_t>((size_t)tiles.size() * kTileSums, 1)));
+    HIP_TRY(c, c->d_cdesc.ensure(std::max<size_t>(c->cdesc.size(), 1)));
+    if (!items.empty()) {
+        HIP_TRY(c, hipMemcpy(c->d_items.p, items.data(), items.size() * sizeof(SweepItem), hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->d_order.p, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    if (!tiles.empty())
+        HIP_TRY(c, hipMemcpy(c->d_tiles.p, tiles.data(), tiles.size() * sizeof(ITile), hipMemcpyHostToDevice));
+    if (!c->cdesc.empty())
+        HIP_TRY(c, hipMemcpy(c->d_cdesc.p, c->cdesc.data(), c->cdesc.size() * sizeof(ClusterDesc),
+                             hipMemcpyHostToDevice));
+    if (tiles_out) *tiles_out = tiles;
+    c->plan_ok = true;
+    return SCMD_OK;
+}
+
+int ensure_plan(scmd_ctx *c) {
+    if (c->plan_ok) return SCMD_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    std::vector<ITile> tiles;
+    int rc = build_plan(c, &tiles);
+    if (rc != SCMD_OK) return rc;
+    if (c->neighbour == SCMD_CELLLIST) {
+        if (!c->cells) c->cells = cell_list_create();
+        if (!c->cells) return fail(c, SCMD_ENOMEM, "cell list allocation failed");
+        hipError_t e = cell_list_plan(c->cells, c->nclusters, c->offsets.data(), c->params.rc, tiles.data(),
+                                      c->ntiles, c->tile);
+        if (e != hipSuccess) return fail(c, SCMD_EDEVICE, std::string("cell list plan: ") + hipGetErrorString(e));
+    }
+    return SCMD_OK;
+}
+
+// -------------------------------------------------------------------------
+// Enqueue
+// -------------------------------------------------------------------------
+hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing) {
+    int ev = -1;
+    if (c->profiling && (!capturing || c->graph_events_ok)) {
+        ev = take_event(c, force ? SCMD_KERNEL_FORCE : SCMD_KERNEL_DENSITY);
+        if (ev >= 0) {
+            hipError_t e = hipEventRecord(c->evs[ev].a, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    hipError_t e;
+    if (c->neighbour == SCMD_CELLLIST) {
+        e = force ? cell_list_force(c->cells, c->rp.p, c->d_part.p, c->pc, c->precision, s)
+                  : cell_list_density(c->cells, c->rp.p, c->d_part.p, c->pc, c->precision, s);
+    } else {
+        SweepLaunch L{c->d_items.p, c->d_order.p, c->nitems, c->block, c->ipt, c->tile};
+        e = force ? launch_force(L, c->rp.p, c->d_part.p, c->pc, c->precision, s)
+                  : launch_density(L, c->rp.p, c->d_part.p, c->pc, c->precision, s);
+    }
+    if (e != hipSuccess) return e;
+    if (ev >= 0) {
+        e = hipEventRecord(c->evs[ev].b, s);
+        if (e != hipSuccess) return e;
+        (capturing ? c->ev_graph : c->ev_pending).push_back(ev);
+    }
+    return hipSuccess;
+}
+
+double half_kick(const scmd_ctx *c) { return 0.5 * c->dt / (c->mass * kEvPerUA2Fs2); }
+
+// rho, F, energies at the current positions; advance = 1 also kicks and
+// runs the thermostat (second half of a step).
+hipError_t enqueue_forces(scmd_ctx *c, hipStream_t s, bool capturing, int advance) {
+    hipError_t e;
+    if (c->neighbour == SCMD_CELLLIST) {
+        if ((e = cell_list_build(c->cells, c->rp.p, s)) != hipSuccess) return e;
+    }
+    if ((e = sweep(c, false, s, capturing)) != hipSuccess) return e;
+    e = launch_density_reduce(c->d_tiles.p, c->ntiles, c->tile, c->d_part.p, c->rp.p, c->rho.p, c->d_tile_sums.p,
+                              c->pc, s);
+    if (e != hipSuccess) return e;
+    if ((e = sweep(c, true, s, capturing)) != hipSuccess) return e;
+    e = launch_force_reduce(c->d_tiles.p, c->ntiles, c->tile, c->d_part.p, c->f.p, c->v.p, c->d_tile_sums.p, c->pc,
+                            half_kick(c), advance, s);
+    if (e != hipSuccess) return e;
+    return launch_finalize(c->d_cdesc.p, c->d_state.p, c->nclusters, c->d_tile_sums.p, c->mass, c->dt, advance,
+                           c->d_flag.p, s);
+}
+
+hipError_t enqueue_step(scmd_ctx *c, hipStream_t s, bool capturing) {
+    hipError_t e = launch_drift(c->atom_cluster.p, c->d_state.p, c->rp.p, c->v.p, c->f.p, c->natoms, c->dt,
+                                half_kick(c), s);
+    if (e != hipSuccess) return e;
+    return enqueue_forces(c, s, capturing, 1);
+}
+
+int ensure_graph(scmd_ctx *c) {
+    if (c->graph && c->graph_profiled == c->profiling) return SCMD_OK;
+    drop_graph(c);
+    hipGraph_t g = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) e = enqueue_step(c, c->cap_stream, true);
+    hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        for (int i : c->ev_graph) c->ev_free.push_back(i);
+        c->ev_graph.clear();
+        if (c->profiling && c->graph_events_ok) {
+            // event records inside capture unsupported: profile eagerly instead
+            c->graph_events_ok = false;
+            (void)hipGetLastError();
+            return ensure_graph(c);
+        }
+        return fail(c, SCMD_EDEVICE, std::string("graph capture failed: ") +
+                                         hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipError_t e3 = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) {
+        c->graph = nullptr;
+        return fail(c, SCMD_EDEVICE, std::string("graph instantiate failed: ") + hipGetErrorString(e3));
+    }
+    c->graph_profiled = c->profiling;
+    return SCMD_OK;
+}
+
+int check_ready(scmd_ctx *c) {
+    if (!c) return SCMD_EINVAL;
+    if (!ready(c)) return fail(c, SCMD_ESTATE, "init_clusters, set_potential and set_integrator must come first");
+    return SCMD_OK;
+}
+
+int sync_and_check(scmd_ctx *c) {
+    HIP_TRY(c, hipMemcpyAsync(c->h_flag, c->d_flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->profiling) harvest_events(c);
+    if (*c->h_flag) return fail(c, SCMD_ENONFINITE, "a cluster energy became non-finite (coincident or overlapping atoms?)");
+    return SCMD_OK;
+}
+
+int enqueue_steps(scmd_ctx *c, int64_t nsteps) {
+    int rc = ensure_plan(c);
+    if (rc != SCMD_OK) return rc;
+    if (c->neighbour == SCMD_CELLLIST && cell_list_overflowed(c->cells))
+        return fail(c, SCMD_EBOX, "cell grid exceeded its cap");
+    if (!c->have_forces) {
+        HIP_TRY(c, enqueue_forces(c, c->stream, false, 0));
+        c->have_forces = true;
+    }
+    const bool use_graph = !(c->profiling && !c->graph_events_ok);
+    int64_t full = use_graph ? nsteps / kGraphSteps : 0;
+    int64_t rem = nsteps - full * kGraphSteps;
+    if (full > 0) {
+        rc = ensure_graph(c);
+        if (rc != SCMD_OK) return rc;
+        for (int64_t r = 0; r < full; ++r) HIP_TRY(c, hipGraphLaunch(c->graph, c->stream));
+        c->graph_unread = c->profiling != 0;
+    }
+    for (int64_t r = 0; r < rem; ++r) HIP_TRY(c, enqueue_step(c, c->stream, false));
+    c->step += nsteps;
+    return SCMD_OK;
+}
+
+int copy_state_table(scmd_ctx *c, std::vector<ClusterState> &st) {
+    st.resize(c->nclusters);
+    if (c->nclusters > 0)
+        HIP_TRY(c, hipMemcpy(st.data(), c->d_state.p, st.size() * sizeof(ClusterState), hipMemcpyDeviceToHost));
+    return SCMD_OK;
+}
+
+int copy_aos(scmd_ctx *c, const double4 *src, double *out, const std::vector<double> *scale_per_atom) {
+    std::vector<double4> tmp(c->natoms);
+    if (c->natoms > 0)
+        HIP_TRY(c, hipMemcpy(tmp.data(), src, tmp.size() * sizeof(double4), hipMemcpyDeviceToHost));
+    for (int i = 0; i < c->natoms; ++i) {
+        double s = scale_per_atom ? (*scale_per_atom)[i] : 1.0;
+        if (scale_per_atom) {
+            out[3 * i + 0] = s * tmp[i].x;
+            out[3 * i + 1] = s * tmp[i].y;
+            out[3 * i + 2] = s * tmp[i].z;
+        } else {
+            out[3 * i + 0] = tmp[i].x;
+            out[3 * i + 1] = tmp[i].y;
+            out[3 * i + 2] = tmp[i].z;
+        }
+    }
+    return SCMD_OK;
+}
+
+void release_device(scmd_ctx *c) {
+    drop_graph(c);
+    c->rp.release();
+    c->v.release();
+    c->f.release();
+    c->rho.release();
+    c->atom_cluster.release();
+    c->d_cdesc.release();
+    c->d_state.release();
+    c->d_items.release();
+    c->d_order.release();
+    c->d_tiles.release();
+    c->d_part.release();
+    c->d_tile_sums.release();
+    if (c->cells) {
+        cell_list_destroy(c->cells);
+        c->cells = nullptr;
+    }
+}
+
+struct StateHeader {
+    char magic[8];
+    int32_t version;
+    int32_t nclusters;
+    int64_t natoms;
+    int64_t step;
+    int32_t have_forces;
+    int32_t pad;
+};
+
+size_t state_bytes(const scmd_ctx *c) {
+    return sizeof(StateHeader) + (c->nclusters + 1) * sizeof(int64_t) + 3 * (size_t)c->natoms * sizeof(double4) +
+           (size_t)c->natoms * sizeof(double) + (size_t)c->nclusters * (sizeof(ClusterDesc) + sizeof(ClusterState));
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int scmd_abi_version(void) { return SCMD_ABI_VERSION; }
+
+const char *scmd_status_string(int status) {
+    switch (status) {
+        case SCMD_OK: return "ok";
+        case SCMD_EINVAL: return "invalid argument";
+        case SCMD_ENOMEM: return "out of memory";
+        case SCMD_EDEVICE: return "device or HIP runtime error";
+        case SCMD_ENONFINITE: return "non-finite energy";
+        case SCMD_ESTATE: return "call out of order";
+        case SCMD_EBOX: return "cell grid cap exceeded";
+        case SCMD_EUNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+const char *scmd_last_error(const scmd_ctx *ctx) {
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+int scmd_create(scmd_ctx **out, int device, void *hip_stream) {
+    if (!out) {
+        g_create_error = "out is NULL";
+        return SCMD_EINVAL;
+    }
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
+        g_create_error = std::string("no HIP device: ") + (e != hipSuccess ? hipGetErrorString(e) : "count is 0");
+        return SCMD_EDEVICE;
+    }
+    if (device < 0 || device >= count) {
+        g_create_error = "device index out of range";
+        return SCMD_EDEVICE;
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipGetDeviceProperties: ") + hipGetErrorString(e);
+        return SCMD_EDEVICE;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        g_create_error = std::string("this library is built for gfx950, device is ") + prop.gcnArchName;
+        return SCMD_EDEVICE;
+    }
+    scmd_ctx *c = nullptr;
+    try {
+        c = new scmd_ctx();
+    } catch (...) {
+        g_create_error = "host allocation failed";
+        return SCMD_ENOMEM;
+    }
+    c->device = device;
+    if ((e = hipSetDevice(device)) != hipSuccess) {
+        delete c;
+        g_create_error = std::string("hipSetDevice: ") + hipGetErrorString(e);
+        return SCMD_EDEVICE;
+    }
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
+            delete c;
+            g_create_error = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+            return SCMD_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    if ((e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&c->h_flag, sizeof(int), hipHostMallocDefault)) != hipSuccess ||
+        (e = c->d_flag.ensure(1)) != hipSuccess) {
+        g_create_error = std::string("context setup: ") + hipGetErrorString(e);
+        scmd_destroy(c);
+        return SCMD_EDEVICE;
+    }
+    *c->h_flag = 0;
+    if ((e = hipMemset(c->d_flag.p, 0, sizeof(int))) != hipSuccess) {
+        g_create_error = std::string("hipMemset: ") + hipGetErrorString(e);
+        scmd_destroy(c);
+        return SCMD_EDEVICE;
+    }
+    *out = c;
+    return SCMD_OK;
+}
+
+int scmd_destroy(scmd_ctx *ctx) {
+    if (!ctx) return SCMD_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    release_device(ctx);
+    ctx->d_flag.release();
+    for (auto &e : ctx->evs) {
+        if (e.a) (void)hipEventDestroy(e.a);
+        if (e.b) (void)hipEventDestroy(e.b);
+    }
+    if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return SCMD_OK;
+}
+
+int scmd_init_clusters(scmd_ctx *ctx, int n_clusters, const int64_t *offsets, const double *pos, const double *vel,
+                       double mass_u) {
+    if (!ctx) return SCMD_EINVAL;
+    SCMD_GUARD({
+        if (n_clusters < 1 || !offsets) return fail(ctx, SCMD_EINVAL, "need n_clusters >= 1 and offsets");
+        if (!(mass_u > 0.0) || !std::isfinite(mass_u)) return fail(ctx, SCMD_EINVAL, "mass_u must be > 0");
+        if (offsets[0] != 0) return fail(ctx, SCMD_EINVAL, "offsets[0] must be 0");
+        for (int k = 0; k < n_clusters; ++k)
+            if (offsets[k + 1] < offsets[k]) return fail(ctx, SCMD_EINVAL, "offsets must be non-decreasing");
+        const int64_t natoms = offsets[n_clusters];
+        if (natoms >= (int64_t(1) << 30)) return fail(ctx, SCMD_EINVAL, "too many atoms (limit 2^30)");
+        if (natoms > 0 && !pos) return fail(ctx, SCMD_EINVAL, "pos is NULL");
+        for (int64_t i = 0; i < 3 * natoms; ++i) {
+            if (!std::isfinite(pos[i]) || (vel && !std::isfinite(vel[i])))
+                return fail(ctx, SCMD_EINVAL, "non-finite position or velocity");
+            if (std::fabs(pos[i]) > 1e12) return fail(ctx, SCMD_EINVAL, "position beyond 1e12 A");
+        }
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        release_device(ctx);
+        ctx->have_clusters = false;
+        ctx->plan_ok = false;
+        ctx->have_forces = false;
+        ctx->step = 0;
+        ctx->nclusters = n_clusters;
+        ctx->natoms = (int)natoms;
+        ctx->mass = mass_u;
+        ctx->offsets.assign(offsets, offsets + n_clusters + 1);
+        ctx->cdesc.assign(n_clusters, ClusterDesc{});
+        for (auto &d : ctx->cdesc) {
+            d.kind = SCMD_NVE;
+            d.tau = 100.0;
+        }
+        std::vector<double4> r4(natoms), v4(natoms);
+        std::vector<int32_t> ac(natoms);
+        for (int64_t i = 0; i < natoms; ++i) {
+            r4[i] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 0.0);
+            v4[i] = vel ? make_double4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 0.0) : make_double4(0, 0, 0, 0);
+        }
+        for (int k = 0; k < n_clusters; ++k)
+            for (int64_t i = offsets[k]; i < offsets[k + 1]; ++i) ac[i] = k;
+        const size_t na = std::max<int64_t>(natoms, 1);
+        HIP_TRY(ctx, ctx->rp.ensure(na));
+        HIP_TRY(ctx, ctx->v.ensure(na));
+        HIP_TRY(ctx, ctx->f.ensure(na));
+        HIP_TRY(ctx, ctx->rho.ensure(na));
+        HIP_TRY(ctx, ctx->atom_cluster.ensure(na));
+        HIP_TRY(ctx, ctx->d_state.ensure(n_clusters));
+        HIP_TRY(ctx, ctx->d_cdesc.ensure(n_clusters));
+        if (natoms > 0) {
+            HIP_TRY(ctx, hipMemcpy(ctx->rp.p, r4.data(), natoms * sizeof(double4), hipMemcpyHostToDevice));
+            HIP_TRY(ctx, hipMemcpy(ctx->v.p, v4.data(), natoms * sizeof(double4), hipMemcpyHostToDevice));
+            HIP_TRY(ctx, hipMemcpy(ctx->atom_cluster.p, ac.data(), natoms * sizeof(int32_t), hipMemcpyHostToDevice));
+            HIP_TRY(ctx, hipMemset(ctx->f.p, 0, natoms * sizeof(double4)));
+            HIP_TRY(ctx, hipMemset(ctx->rho.p, 0, natoms * sizeof(double)));
+        }
+        std::vector<ClusterState> st(n_clusters);
+        for (auto &s : st) {
+            std::memset(&s, 0, sizeof(s));
+            s.lambda = 1.0;
+        }
+        HIP_TRY(ctx, hipMemcpy(ctx->d_state.p, st.data(), st.size() * sizeof(ClusterState), hipMemcpyHostToDevice));
+        HIP_TRY(ctx, hipMemset(ctx->d_flag.p, 0, sizeof(int)));
+        *ctx->h_flag = 0;
+        ctx->have_clusters = true;
+        return SCMD_OK;
+    })
+}
+
+int scmd_set_potential(scmd_ctx *ctx, const scmd_sc_params *p) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!p) return fail(ctx, SCMD_EINVAL, "params is NULL");
+    if (!(p->eps > 0.0) || !(p->a > 0.0) || !(p->c >= 0.0) || !std::isfinite(p->eps) || !std::isfinite(p->a) ||
+        !std::isfinite(p->c))
+        return fail(ctx, SCMD_EINVAL, "need eps > 0, a > 0, c >= 0");
+    if (p->m < 1 || p->n <= p->m || p->n > 24) return fail(ctx, SCMD_EINVAL, "need 1 <= m < n <= 24");
+    if (!(p->rc >= 0.0) || !std::isfinite(p->rc)) return fail(ctx, SCMD_EINVAL, "need rc >= 0");
+    if (ctx->have_integ) {
+        if (ctx->neighbour == SCMD_ALLPAIRS && p->rc > 0.0)
+            return fail(ctx, SCMD_EINVAL, "all-pairs mode needs rc == 0 (use SCMD_CELLLIST for a cutoff)");
+        if (ctx->neighbour == SCMD_CELLLIST && !(p->rc > 0.0))
+            return fail(ctx, SCMD_EINVAL, "cell-list mode needs rc > 0");
+    }
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->params = *p;
+    ctx->pc = make_pot(*p);
+    ctx->have_pot = true;
+    ctx->have_forces = false;
+    ctx->plan_ok = false;
+    drop_graph(ctx);
+    return SCMD_OK;
+}
+
+int scmd_set_integrator(scmd_ctx *ctx, double dt_fs, int precision, int neighbour) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!(dt_fs > 0.0) || !std::isfinite(dt_fs)) return fail(ctx, SCMD_EINVAL, "need dt_fs > 0");
+    if (precision != SCMD_FP64 && precision != SCMD_MIXED) return fail(ctx, SCMD_EINVAL, "unknown precision");
+    if (neighbour != SCMD_ALLPAIRS && neighbour != SCMD_CELLLIST) return fail(ctx, SCMD_EINVAL, "unknown neighbour mode");
+    if (ctx->have_pot) {
+        if (neighbour == SCMD_ALLPAIRS && ctx->params.rc > 0.0)
+            return fail(ctx, SCMD_EINVAL, "all-pairs mode needs rc == 0 (use SCMD_CELLLIST for a cutoff)");
+        if (neighbour == SCMD_CELLLIST && !(ctx->params.rc > 0.0))
+            return fail(ctx, SCMD_EINVAL, "cell-list mode needs rc > 0");
+    }
+    if (neighbour == SCMD_CELLLIST && !cell_list_available())
+        return fail(ctx, SCMD_EUNSUPPORTED, "cell-list mode is not built into this library");
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->dt = dt_fs;
+    ctx->precision = precision;
+    ctx->neighbour = neighbour;
+    ctx->have_integ = true;
+    ctx->have_forces = false;
+    ctx->plan_ok = false;
+    drop_graph(ctx);
+    return SCMD_OK;
+}
+
+int scmd_set_thermostat(scmd_ctx *ctx, int cluster, int kind, double T_start_K, double T_end_K, int64_t ramp_steps,
+                        double tau_fs) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
+    if (cluster < -1 || cluster >= ctx->nclusters) return fail(ctx, SCMD_EINVAL, "cluster index out of range");
+    if (kind == SCMD_LANGEVIN) return fail(ctx, SCMD_EUNSUPPORTED, "Langevin thermostat not provided");
+    if (kind != SCMD_NVE && kind != SCMD_BERENDSEN) return fail(ctx, SCMD_EINVAL, "unknown thermostat kind");
+    if (kind == SCMD_BERENDSEN) {
+        if (!(tau_fs > 0.0) || !std::isfinite(tau_fs)) return fail(ctx, SCMD_EINVAL, "need tau_fs > 0");
+        if (!(T_start_K >= 0.0) || !(T_end_K >= 0.0) || !std::isfinite(T_start_K) || !std::isfinite(T_end_K))
+            return fail(ctx, SCMD_EINVAL, "temperatures must be finite and >= 0");
+    }
+    const int a = cluster < 0 ? 0 : cluster, b = cluster < 0 ? ctx->nclusters : cluster + 1;
+    for (int k = a; k < b; ++k) {
+        ClusterDesc &d = ctx->cdesc[k];
+        d.kind = kind;
+        if (kind == SCMD_BERENDSEN) {
+            d.T_start = T_start_K;
+            d.T_end = T_end_K;
+            d.ramp = ramp_steps;
+            d.tau = tau_fs;
+        }
+    }
+    if (ctx->plan_ok && ctx->d_cdesc.p) {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        HIP_TRY(ctx, hipMemcpy(ctx->d_cdesc.p, ctx->cdesc.data(), ctx->cdesc.size() * sizeof(ClusterDesc),
+                               hipMemcpyHostToDevice));
+    }
+    return SCMD_OK;
+}
+
+int scmd_set_tuning(scmd_ctx *ctx, const scmd_tuning *t) {
+    if (!ctx) return SCMD_EINVAL;
+    scmd_tuning z{};
+    if (t) {
+        if (t->block != 0 && t->block != 64 && t->block != 128 && t->block != 256)
+            return fail(ctx, SCMD_EINVAL, "block must be 64, 128 or 256");
+        if (t->ipt != 0 && t->ipt != 1 && t->ipt != 2 && t->ipt != 4)
+            return fail(ctx, SCMD_EINVAL, "ipt must be 1, 2 or 4");
+        if (t->target_items < 0) return fail(ctx, SCMD_EINVAL, "target_items must be >= 0");
+        z = *t;
+    }
+    ctx->tuning = z;
+    ctx->plan_ok = false;
+    return SCMD_OK;
+}
+
+int scmd_compute(scmd_ctx *ctx) {
+    int rc = check_ready(ctx);
+    if (rc != SCMD_OK) return rc;
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        rc = ensure_plan(ctx);
+        if (rc != SCMD_OK) return rc;
+        if (ctx->neighbour == SCMD_CELLLIST && cell_list_overflowed(ctx->cells))
+            return fail(ctx, SCMD_EBOX, "cell grid exceeded its cap");
+        HIP_TRY(ctx, enqueue_forces(ctx, ctx->stream, false, 0));
+        ctx->have_forces = true;
+        rc = sync_and_check(ctx);
+        if (rc == SCMD_OK && ctx->neighbour == SCMD_CELLLIST && cell_list_overflowed(ctx->cells))
+            return fail(ctx, SCMD_EBOX, "cell grid exceeded its cap");
+        return rc;
+    })
+}
+
+int scmd_step_async(scmd_ctx *ctx, int64_t nsteps) {
+    int rc = check_ready(ctx);
+    if (rc != SCMD_OK) return rc;
+    if (nsteps < 0) return fail(ctx, SCMD_EINVAL, "nsteps must be >= 0");
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        if (*ctx->h_flag) return fail(ctx, SCMD_ENONFINITE, "a previous step produced a non-finite energy");
+        return enqueue_steps(ctx, nsteps);
+    })
+}
+
+int scmd_synchronize(scmd_ctx *ctx) {
+    if (!ctx) return SCMD_EINVAL;
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        if (!ctx->have_clusters) {
+            HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+            return SCMD_OK;
+        }
+        int rc = sync_and_check(ctx);
+        if (rc == SCMD_OK && ctx->neighbour == SCMD_CELLLIST && ctx->cells && cell_list_overflowed(ctx->cells))
+            return fail(ctx, SCMD_EBOX, "cell grid exceeded its cap");
+        return rc;
+    })
+}
+
+int scmd_step(scmd_ctx *ctx, int64_t nsteps) {
+    int rc = scmd_step_async(ctx, nsteps);
+    if (rc != SCMD_OK) return rc;
+    return scmd_synchronize(ctx);
+}
+
+int scmd_get_step(scmd_ctx *ctx, int64_t *step) {
+    if (!ctx || !step) return SCMD_EINVAL;
+    *step = ctx->step;
+    return SCMD_OK;
+}
+
+int scmd_get_energy(scmd_ctx *ctx, int cluster, double out3[3]) {
+    int rc = check_ready(ctx);
+    if (rc != SCMD_OK) return rc;
+    if (!out3) return fail(ctx, SCMD_EINVAL, "out is NULL");
+    if (cluster < -1 || cluster >= ctx->nclusters) return fail(ctx, SCMD_EINVAL, "cluster index out of range");
+    if (!ctx->have_forces) return fail(ctx, SCMD_ESTATE, "compute or step first");
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        rc = sync_and_check(ctx);
+        if (rc != SCMD_OK) return rc;
+        std::vector<ClusterState> st;
+        rc = copy_state_table(ctx, st);
+        if (rc != SCMD_OK) return rc;
+        double ep = 0.0, ek = 0.0;
+        for (int k = 0; k < ctx->nclusters; ++k) {
+            if (cluster >= 0 && k != cluster) continue;
+            ep += st[k].epot;
+            ek += st[k].ekin;
+        }
+        out3[0] = ep;
+        out3[1] = ek;
+        out3[2] = ep + ek;
+        return SCMD_OK;
+    })
+}
+
+int scmd_get_temperature(scmd_ctx *ctx, int cluster, double *T_K, int64_t *ndof) {
+    int rc = check_ready(ctx);
+    if (rc != SCMD_OK) return rc;
+    if (!T_K) return fail(ctx, SCMD_EINVAL, "T_K is NULL");
+    if (cluster < 0 || cluster >= ctx->nclusters) return fail(ctx, SCMD_EINVAL, "cluster index out of range");
+    if (!ctx->have_forces) return fail(ctx, SCMD_ESTATE, "compute or step first");
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        rc = sync_and_check(ctx);
+        if (rc != SCMD_OK) return rc;
+        std::vector<ClusterState> st;
+        rc = copy_state_table(ctx, st);
+        if (rc != SCMD_OK) return rc;
+        *T_K = st[cluster].temp;
+        if (ndof) *ndof = ndof_of(ctx->offsets[cluster + 1] - ctx->offsets[cluster]);
+        return SCMD_OK;
+    })
+}
+
+int scmd_get_positions(scmd_ctx *ctx, double *out) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
+    if (!out && ctx->natoms > 0) return fail(ctx, SCMD_EINVAL, "out is NULL");
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        return copy_aos(ctx, ctx->rp.p, out, nullptr);
+    })
+}
+
+int scmd_get_velocities(scmd_ctx *ctx, double *out) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
+    if (!out && ctx->natoms > 0) return fail(ctx, SCMD_EINVAL, "out is NULL");
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        std::vector<ClusterState> st;
+        int rc = copy_state_table(ctx, st);
+        if (rc != SCMD_OK) return rc;
+        std::vector<double> lam(ctx->natoms);
+        for (int k = 0; k < ctx->nclusters; ++k)
+            for (int64_t i = ctx->offsets[k]; i < ctx->offsets[k + 1]; ++i) lam[i] = st[k].lambda;
+        return copy_aos(ctx, ctx->v.p, out, &lam);
+    })
+}
+
+int scmd_get_forces(scmd_ctx *ctx, double *out) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
+    if (!ctx->have_forces) return fail(ctx, SCMD_ESTATE, "compute or step first");
+    if (!out && ctx->natoms > 0) return fail(ctx, SCMD_EINVAL, "out is NULL");
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        return copy_aos(ctx, ctx->f.p, out, nullptr);
+    })
+}
+
+int scmd_get_density(scmd_ctx *ctx, double *out) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
+    if (!ctx->have_forces) return fail(ctx, SCMD_ESTATE, "compute or step first");
+    if (!out && ctx->natoms > 0) return fail(ctx, SCMD_EINVAL, "out is NULL");
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        if (ctx->natoms > 0)
+            HIP_TRY(ctx, hipMemcpy(out, ctx->rho.p, ctx->natoms * sizeof(double), hipMemcpyDeviceToHost));
+        return SCMD_OK;
+    })
+}
+
+int scmd_get_forces_device(scmd_ctx *ctx, double *dev_out) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
+    if (!ctx->have_forces) return fail(ctx, SCMD_ESTATE, "compute or step first");
+    if (!dev_out && ctx->natoms > 0) return fail(ctx, SCMD_EINVAL, "dev_out is NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_aos_from4(ctx->f.p, dev_out, ctx->natoms, ctx->stream));
+    return SCMD_OK;
+}
+
+int scmd_get_state(scmd_ctx *ctx, void *buf, size_t *bytes) {
+    if (!ctx || !bytes) return SCMD_EINVAL;
+    if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
+    const size_t need = state_bytes(ctx);
+    if (!buf) {
+        *bytes = need;
+        return SCMD_OK;
+    }
+    if (*bytes < need) return fail(ctx, SCMD_EINVAL, "buffer too small");
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        char *p = (char *)buf;
+        StateHeader h{};
+        std::memcpy(h.magic, "SCMDSTA1", 8);
+        h.version = 1;
+        h.nclusters = ctx->nclusters;
+        h.natoms = ctx->natoms;
+        h.step = ctx->step;
+        h.have_forces = ctx->have_forces ? 1 : 0;
+        std::memcpy(p, &h, sizeof(h));
+        p += sizeof(h);
+        std::memcpy(p, ctx->offsets.data(), (ctx->nclusters + 1) * sizeof(int64_t));
+        p += (ctx->nclusters + 1) * sizeof(int64_t);
+        const size_t n4 = (size_t)ctx->natoms * sizeof(double4);
+        if (ctx->natoms > 0) {
+            HIP_TRY(ctx, hipMemcpy(p, ctx->rp.p, n4, hipMemcpyDeviceToHost));
+            HIP_TRY(ctx, hipMemcpy(p + n4, ctx->v.p, n4, hipMemcpyDeviceToHost));
+            HIP_TRY(ctx, hipMemcpy(p + 2 * n4, ctx->f.p, n4, hipMemcpyDeviceToHost));
+            HIP_TRY(ctx, hipMemcpy(p + 3 * n4, ctx->rho.p, ctx->natoms * sizeof(double), hipMemcpyDeviceToHost));
+        }
+        p += 3 * n4 + (size_t)ctx->natoms * sizeof(double);
+        std::memcpy(p, ctx->cdesc.data(), ctx->nclusters * sizeof(ClusterDesc));
+        p += ctx->nclusters * sizeof(ClusterDesc);
+        HIP_TRY(ctx, hipMemcpy(p, ctx->d_state.p, ctx->nclusters * sizeof(ClusterState), hipMemcpyDeviceToHost));
+        *bytes = need;
+        return SCMD_OK;
+    })
+}
+
+int scmd_set_state(scmd_ctx *ctx, const void *buf, size_t bytes) {
+    if (!ctx || !buf) return SCMD_EINVAL;
+    if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
+    if (bytes < sizeof(StateHeader)) return fail(ctx, SCMD_EINVAL, "blob too small");
+    StateHeader h;
+    std::memcpy(&h, buf, sizeof(h));
+    if (std::memcmp(h.magic, "SCMDSTA1", 8) != 0 || h.version != 1) return fail(ctx, SCMD_EINVAL, "not a state blob");
+    if (h.nclusters != ctx->nclusters || h.natoms != ctx->natoms || bytes != state_bytes(ctx))
+        return fail(ctx, SCMD_EINVAL, "blob has a different cluster layout");
+    const char *p = (const char *)buf + sizeof(h);
+    if (std::memcmp(p, ctx->offsets.data(), (ctx->nclusters + 1) * sizeof(int64_t)) != 0)
+        return fail(ctx, SCMD_EINVAL, "blob has different cluster offsets");
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        p += (ctx->nclusters + 1) * sizeof(int64_t);
+        const size_t n4 = (size_t)ctx->natoms * sizeof(double4);
+        if (ctx->natoms > 0) {
+            HIP_TRY(ctx, hipMemcpy(ctx->rp.p, p, n4, hipMemcpyHostToDevice));
+            HIP_TRY(ctx, hipMemcpy(ctx->v.p, p + n4, n4, hipMemcpyHostToDevice));
+            HIP_TRY(ctx, hipMemcpy(ctx->f.p, p + 2 * n4, n4, hipMemcpyHostToDevice));
+            HIP_TRY(ctx, hipMemcpy(ctx->rho.p, p + 3 * n4, ctx->natoms * sizeof(double), hipMemcpyHostToDevice));
+        }
+        p += 3 * n4 + (size_t)ctx->natoms * sizeof(double);
+        std::vector<ClusterDesc> cd(ctx->nclusters);
+        std::memcpy(cd.data(), p, ctx->nclusters * sizeof(ClusterDesc));
+        for (int k = 0; k < ctx->nclusters; ++k) {
+            ctx->cdesc[k].kind = cd[k].kind;
+            ctx->cdesc[k].T_start = cd[k].T_start;
+            ctx->cdesc[k].T_end = cd[k].T_end;
+            ctx->cdesc[k].tau = cd[k].tau;
+            ctx->cdesc[k].ramp = cd[k].ramp;
+        }
+        p += ctx->nclusters * sizeof(ClusterDesc);
+        HIP_TRY(ctx, hipMemcpy(ctx->d_state.p, p, ctx->nclusters * sizeof(ClusterState), hipMemcpyHostToDevice));
+        if (ctx->plan_ok)
+            HIP_TRY(ctx, hipMemcpy(ctx->d_cdesc.p, ctx->cdesc.data(), ctx->nclusters * sizeof(ClusterDesc),
+                                   hipMemcpyHostToDevice));
+        ctx->step = h.step;
+        ctx->have_forces = h.have_forces != 0;
+        HIP_TRY(ctx, hipMemset(ctx->d_flag.p, 0, sizeof(int)));
+        *ctx->h_flag = 0;
+        return SCMD_OK;
+    })
+}
+
+int scmd_set_profiling(scmd_ctx *ctx, int enable) {
+    if (!ctx) return SCMD_EINVAL;
+    ctx->profiling = enable ? 1 : 0;
+    for (int k = 0; k < SCMD_KERNEL_COUNT; ++k) {
+        ctx->prof_ms[k] = 0.0;
+        ctx->prof_n[k] = 0;
+    }
+    return SCMD_OK;
+}
+
+int scmd_get_kernel_time(scmd_ctx *ctx, int kernel, double *avg_ms, int64_t *launches) {
+    if (!ctx || !avg_ms) return SCMD_EINVAL;
+    if (kernel < 0 || kernel >= SCMD_KERNEL_COUNT) return fail(ctx, SCMD_EINVAL, "unknown kernel class");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    harvest_events(ctx);
+    *avg_ms = ctx->prof_n[kernel] > 0 ? ctx->prof_ms[kernel] / (double)ctx->prof_n[kernel] : 0.0;
+    if (launches) *launches = ctx->prof_n[kernel];
+    return SCMD_OK;
+}
+
+}  // extern "C"

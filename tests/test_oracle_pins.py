@@ -369,3 +369,12 @@ def test_berendsen_ramp_target(oracle_mod):
     assert oracle_mod.target_temperature(2000.0, 800.0, 200000, 100000) == pytest.approx(1400.0, rel=1e-15)
     assert oracle_mod.target_temperature(2000.0, 800.0, 200000, 10 ** 7) == 800.0
     assert oracle_mod.target_temperature(2000.0, 800.0, 0, 5) == 800.0
+
+
+def test_subset_forces_equal_full_forces(oracle_mod):
+    pos = _cluster(200, 0.2, 4)
+    f, rho, _ = oracle_mod.forces(pos)
+    idx = np.array([0, 17, 199, 5])
+    fs, rho_s = oracle_mod.forces_subset(pos, idx)
+    np.testing.assert_array_equal(fs, f[idx])
+    np.testing.assert_array_equal(rho_s, rho)
