@@ -64,16 +64,17 @@ enum {
     SCMD_EDEVICE = -3,      /* no usable gfx950 device or a HIP runtime error       */
     SCMD_ENONFINITE = -4,   /* a non-finite energy appeared (e.g. coincident atoms) */
     SCMD_ESTATE = -5,       /* call out of order                                    */
-    SCMD_EBOX = -6,         /* cell grid would exceed its cap (atom escaped far)    */
+    SCMD_EBOX = -6,         /* reserved: the cell list coarsens its cells instead   */
     SCMD_EUNSUPPORTED = -7  /* valid request this build does not implement          */
 };
 
 /* Arithmetic of the pair sweeps. */
 enum {
     SCMD_FP64 = 0,  /* every operation in double precision                          */
-    SCMD_MIXED = 1  /* r_i - r_j in double, then r^2, powers and the pair
-                       coefficient in single precision; each term added to double
-                       accumulators; positions, velocities and integration double */
+    SCMD_MIXED = 1  /* r_i - r_j and r^2 in double, then 1/r, the powers and the
+                       pair coefficient in single precision; each term added to
+                       double accumulators (force terms as f * (r_i - r_j) in
+                       double); positions, velocities and integration double    */
 };
 
 /* Neighbour handling. */
@@ -101,15 +102,21 @@ typedef struct {
     double rc;
 } scmd_sc_params;
 
-/* Launch shape of the pair sweeps (all zero = library defaults).
- * block: threads per workgroup (64, 128 or 256); ipt: atoms owned per thread
- * (1, 2 or 4); target_items: aim for about this many workgroups per sweep when
- * splitting the j range of each atom tile (0 = default). */
+/* Launch shape of the all-pairs sweeps (all zero = library defaults).
+ * An atom tile holds 64 * ipt * waves_i atoms (ipt atoms per lane, waves_i
+ * wavefronts along i); waves_j wavefronts split each tile's partner range
+ * inside a workgroup of 64 * waves_i * waves_j threads.  Supported
+ * (ipt, waves_i, waves_j): (1,4,1) (2,4,1) (1,2,2) (2,2,2) (1,1,4) (2,1,4)
+ * (1,2,4) (2,2,4) (1,4,4) (1,1,8) (2,1,8) (1,2,8) (1,1,16) (4,1,2) (4,1,4)
+ * (4,2,2).  target_items:
+ * aim for about this many workgroups per sweep when splitting partner
+ * ranges across workgroups (0 = default).  Results may differ in the last
+ * bits between shapes (summation order); a given shape is deterministic. */
 typedef struct {
-    int block;
     int ipt;
+    int waves_i;
+    int waves_j;
     int target_items;
-    int reserved;
 } scmd_tuning;
 
 /* Kernel classes timed by scmd_get_kernel_time (device time per launch). */
@@ -219,8 +226,12 @@ int scmd_get_state(scmd_ctx *ctx, void *buf, size_t *bytes);
 int scmd_set_state(scmd_ctx *ctx, const void *buf, size_t bytes);
 
 /* Record device time per launch of the pair sweeps during subsequent
- * scmd_step / scmd_compute calls (HIP events around each launch on the context
- * stream, also inside captured graphs).  enable = 0 stops recording. */
+ * scmd_step / scmd_compute calls: HIP events on the context stream around
+ * every eager launch, and inside each captured graph around the sweeps of its
+ * last step (event nodes between graph kernels cost a few microseconds, so a
+ * graph is sampled once per replay; the sample of the last replay of each
+ * scmd_step call is kept).  enable = 0 stops recording and resets the
+ * averages. */
 int scmd_set_profiling(scmd_ctx *ctx, int enable);
 
 /* Average device milliseconds per launch of a kernel class over the launches

@@ -1,0 +1,106 @@
+"""Launch-shape autotuner for the all-pairs sweeps.
+
+For a workload it times every supported (ipt, waves_i, waves_j) shape and a
+few work-splitting targets with whole velocity-Verlet steps replayed from
+HIP graphs, and keeps the fastest.  Results are cached as JSON keyed by
+(device architecture, precision, cluster-size bucket, cluster count bucket),
+so ``Simulation(..., tuning="auto")`` can pick them up later.
+
+    python -m paper_1210_3559_amd.autotune --workloads ni2243_cooling,batch256 [--cache PATH]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import scmd
+
+SHAPES = [(1, 4, 1), (2, 4, 1), (1, 2, 2), (2, 2, 2), (1, 1, 4), (2, 1, 4), (1, 2, 4), (2, 2, 4), (1, 4, 4),
+          (1, 1, 8), (2, 1, 8), (1, 2, 8), (1, 1, 16), (4, 1, 2), (4, 1, 4), (4, 2, 2)]
+TARGETS = [512, 2048, 8192]
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
+ARCH = "gfx950"
+
+
+def bucket(offsets, precision: str) -> str:
+    sizes = np.diff(np.asarray(offsets))
+    nmax = int(sizes.max()) if len(sizes) else 0
+    return f"{ARCH}/{precision}/nmax2^{max(0, math.ceil(math.log2(max(nmax, 1))))}/nc2^{math.ceil(math.log2(max(len(sizes), 1)))}"
+
+
+def _time(sim: "scmd.Simulation", steps: int) -> float:
+    t0 = time.perf_counter()
+    sim.step(steps)
+    return (time.perf_counter() - t0) / steps
+
+
+def tune(w, precision: str | None = None, budget_s: float = 0.25, shapes=SHAPES, targets=TARGETS, verbose=True):
+    """Time every shape/target on workload w; returns (best tuning dict, table)."""
+    precision = precision or w.precision
+    pairs = float(np.sum(w.sizes().astype(np.float64) ** 2))
+    table = []
+    for ipt, wi, wj in shapes:
+        for tgt in targets:
+            tun = dict(ipt=ipt, waves_i=wi, waves_j=wj, target_items=tgt)
+            with scmd.Simulation.from_workload(w, precision=precision, tuning=tun) as sim:
+                sim.step(32)
+                dt1 = _time(sim, 32)
+                steps = int(max(32, min(4096, budget_s / max(dt1, 1e-7))))
+                steps = 32 * max(1, steps // 32)
+                dt = _time(sim, steps)
+            table.append(dict(tuning=tun, ms_per_step=1e3 * dt))
+            if verbose:
+                print(f"[tune] {w.name} {precision} {tun} {1e3 * dt:.4f} ms/step "
+                      f"({pairs / dt / 1e9:.1f} G ordered pairs/s)", file=sys.stderr, flush=True)
+    best = min(table, key=lambda r: r["ms_per_step"])
+    return best["tuning"], table
+
+
+def load_cache(path: str = DEFAULT_CACHE) -> dict:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def lookup(offsets, precision: str, path: str = DEFAULT_CACHE):
+    """Cached tuning for this cluster layout, or None."""
+    entry = load_cache(path).get(bucket(offsets, precision))
+    return None if entry is None else dict(entry["tuning"])
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workloads", default="ni2243_cooling")
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--cache", default=DEFAULT_CACHE)
+    ap.add_argument("--budget", type=float, default=0.25, help="seconds per timed configuration")
+    ap.add_argument("--report", default=None, help="write the full timing table (JSON) here")
+    args = ap.parse_args(argv)
+    from . import inputs
+    cache = load_cache(args.cache)
+    report = {}
+    for name in args.workloads.split(","):
+        w = inputs.by_name(name)
+        prec = args.precision or w.precision
+        best, table = tune(w, prec, args.budget)
+        key = bucket(w.offsets, prec)
+        cache[key] = dict(tuning=best, ms_per_step=min(r["ms_per_step"] for r in table), workload=w.name)
+        report[w.name] = dict(key=key, best=best, table=table)
+        print(json.dumps(dict(workload=w.name, key=key, best=best, ms=cache[key]["ms_per_step"])), flush=True)
+    with open(args.cache, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump(report, f, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,25 +1,465 @@
-// Cell-list sweeps: placeholder until the cutoff variant lands.
+// Cell-list sweeps for the truncated, shifted Sutton-Chen potential.
+//
+// The paper evaluates all pairs and calls a cutoff future work (Sec. 2,
+// "Computational approach", last paragraphs); this variant truncates both
+// power sums at rc and shifts them to zero there, and finds the pairs with
+// r < rc through a cell list rebuilt every step.
+//
+// Build (every step, every cluster independently, free boundaries):
+//   bbox    one workgroup per cluster: bounding box of its atoms; cells are
+//           boxes of edge h >= rc over it (h grows beyond rc only if the box
+//           would need more cells than the cluster's cell capacity, so an
+//           escaping atom makes cells coarser, never wrong);
+//   count   per atom: its cell, integer atomics count atoms per cell;
+//   scan    exclusive prefix sum of the counts (one workgroup);
+//   scatter per atom: a slot in its cell (atomic cursor);
+//   order   per cell: the slots sorted by atom index, so the cell-sorted
+//           order is deterministic; sorted positions are gathered.
+// Sweeps: one workgroup per cell; its atoms are the lanes (64 per wavefront,
+// chunks beyond that), and the partners are the atoms of the 27 neighbouring
+// cells, read as 9 contiguous x-rows of the sorted arrays with wave-uniform
+// scalar loads.  Every atom's sum is complete after one sweep, so the tiles
+// of the all-pairs plan are finished by the same reduce kernels with one
+// slot per tile.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 #include "cell_list.h"
+#include "sweep_common.h"
 
 namespace scmd {
 
-struct CellList {
-    int dummy;
+struct CellGrid {
+    double ox, oy, oz;  // origin (bounding-box minimum)
+    double hx, hy, hz;  // cell edges (>= rc)
+    int nx, ny, nz;     // cells per dimension this step
+    int cx, cy, cz;     // per-dimension capacity
+    int base;           // first cell of this cluster in the global cell arrays
+    int off, n;         // atoms of the cluster
+    int pad;
 };
 
-bool cell_list_available() { return false; }
-CellList *cell_list_create() { return nullptr; }
-void cell_list_destroy(CellList *) {}
-hipError_t cell_list_plan(CellList *, int, const int64_t *, double, const ITile *, int, int) {
-    return hipErrorNotSupported;
+struct CellList {
+    int nclusters = 0, natoms = 0, total_cap = 0, tile = 0, tile_shift = 0;
+    double rc = 0.0;
+    CellGrid *grid = nullptr;
+    int *cell_cluster = nullptr;  // [total_cap]
+    int *count = nullptr;         // [total_cap]
+    int *start = nullptr;         // [total_cap + 1]
+    int *cursor = nullptr;        // [total_cap]
+    int *cell_of = nullptr;       // [natoms]
+    int *perm = nullptr;          // sorted slot -> atom
+    int *pslot = nullptr;         // atom -> partial index (tile * TILE + li)
+    int *atom_cluster = nullptr;  // [natoms]
+    double4 *rs = nullptr;        // sorted positions (+ P for the force sweep)
+};
+
+namespace {
+
+using namespace dev;
+
+template <typename T>
+hipError_t dalloc(T **p, size_t n) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
 }
-hipError_t cell_list_build(CellList *, const double4 *, hipStream_t) { return hipErrorNotSupported; }
-hipError_t cell_list_density(CellList *, const double4 *, double *, const PotConst &, int, hipStream_t) {
-    return hipErrorNotSupported;
+
+// ---------------------------------------------------------------------------
+// Build kernels
+// ---------------------------------------------------------------------------
+constexpr int kBBoxBlock = 256;
+
+__global__ __launch_bounds__(kBBoxBlock) void k_cell_bbox(CellGrid *__restrict__ grid,
+                                                          const double4 *__restrict__ rp, double rc) {
+    __shared__ double sh[6][kBBoxBlock];
+    CellGrid g = grid[blockIdx.x];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = threadIdx.x; i < g.n; i += kBBoxBlock) {
+        const double4 q = rp[g.off + i];
+        lo[0] = fmin(lo[0], q.x);
+        lo[1] = fmin(lo[1], q.y);
+        lo[2] = fmin(lo[2], q.z);
+        hi[0] = fmax(hi[0], q.x);
+        hi[1] = fmax(hi[1], q.y);
+        hi[2] = fmax(hi[2], q.z);
+    }
+    for (int d = 0; d < 3; ++d) {
+        sh[d][threadIdx.x] = lo[d];
+        sh[3 + d][threadIdx.x] = hi[d];
+    }
+    __syncthreads();
+    for (int s = kBBoxBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            for (int d = 0; d < 3; ++d) {
+                sh[d][threadIdx.x] = fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + s]);
+                sh[3 + d][threadIdx.x] = fmax(sh[3 + d][threadIdx.x], sh[3 + d][threadIdx.x + s]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const int cap[3] = {g.cx, g.cy, g.cz};
+    double o[3], h[3];
+    int n[3];
+    for (int d = 0; d < 3; ++d) {
+        const double ext = g.n > 0 ? sh[3 + d][0] - sh[d][0] : 0.0;
+        o[d] = g.n > 0 ? sh[d][0] : 0.0;
+        double want = floor(ext / rc) + 1.0;
+        if (!(want <= (double)cap[d])) {  // too many cells (or non-finite): coarser cells, edge still >= rc
+            n[d] = cap[d];
+            h[d] = ext / (double)(cap[d] - 1);
+            if (!(h[d] >= rc)) h[d] = rc;
+            if (!isfinite(h[d])) {
+                n[d] = 1;
+                h[d] = INFINITY;
+            }
+        } else {
+            n[d] = (int)want;
+            h[d] = rc;
+        }
+    }
+    g.ox = o[0];
+    g.oy = o[1];
+    g.oz = o[2];
+    g.hx = h[0];
+    g.hy = h[1];
+    g.hz = h[2];
+    g.nx = n[0];
+    g.ny = n[1];
+    g.nz = n[2];
+    grid[blockIdx.x] = g;
 }
-hipError_t cell_list_force(CellList *, const double4 *, double *, const PotConst &, int, hipStream_t) {
-    return hipErrorNotSupported;
+
+__global__ __launch_bounds__(256) void k_cell_clear(int *__restrict__ count, int total) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < total) count[k] = 0;
 }
-bool cell_list_overflowed(CellList *) { return false; }
+
+__device__ __forceinline__ int cell_coord(double x, double o, double h, int n) {
+    const double t = (x - o) / h;
+    int i = t >= 0.0 ? (int)fmin(t, (double)(n - 1)) : 0;
+    return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+}
+
+__global__ __launch_bounds__(256) void k_cell_count(const CellGrid *__restrict__ grid,
+                                                    const int *__restrict__ atom_cluster,
+                                                    const double4 *__restrict__ rp, int *__restrict__ cell_of,
+                                                    int *__restrict__ count, int natoms) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= natoms) return;
+    const CellGrid g = grid[atom_cluster[i]];
+    const double4 q = rp[i];
+    const int ix = cell_coord(q.x, g.ox, g.hx, g.nx);
+    const int iy = cell_coord(q.y, g.oy, g.hy, g.ny);
+    const int iz = cell_coord(q.z, g.oz, g.hz, g.nz);
+    const int cell = g.base + (iz * g.ny + iy) * g.nx + ix;
+    cell_of[i] = cell;
+    atomicAdd(&count[cell], 1);
+}
+
+constexpr int kScanBlock = 1024;
+
+// Exclusive prefix sum of count[0..total) into start[0..total], one workgroup.
+__global__ __launch_bounds__(kScanBlock) void k_cell_scan(const int *__restrict__ count, int *__restrict__ start,
+                                                          int *__restrict__ cursor, int total) {
+    __shared__ int sh[kScanBlock];
+    const int t = threadIdx.x;
+    const int per = (total + kScanBlock - 1) / kScanBlock;
+    const int a = min(total, t * per), b = min(total, a + per);
+    int s = 0;
+    for (int k = a; k < b; ++k) s += count[k];
+    sh[t] = s;
+    __syncthreads();
+    for (int d = 1; d < kScanBlock; d <<= 1) {  // inclusive Hillis-Steele scan of the chunk sums
+        const int v = t >= d ? sh[t - d] : 0;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
+    }
+    int run = sh[t] - s;
+    for (int k = a; k < b; ++k) {
+        start[k] = run;
+        cursor[k] = run;
+        run += count[k];
+    }
+    if (t == kScanBlock - 1) start[total] = sh[t];
+}
+
+__global__ __launch_bounds__(256) void k_cell_scatter(const int *__restrict__ cell_of, int *__restrict__ cursor,
+                                                      int *__restrict__ perm, int natoms) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= natoms) return;
+    perm[atomicAdd(&cursor[cell_of[i]], 1)] = i;
+}
+
+// One thread per cell: sort its slots by atom index (insertion sort; cells
+// hold tens of atoms), then gather the sorted positions.
+__global__ __launch_bounds__(256) void k_cell_order(const int *__restrict__ start, int *__restrict__ perm,
+                                                    const double4 *__restrict__ rp, double4 *__restrict__ rs,
+                                                    int total) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= total) return;
+    const int a = start[k], b = start[k + 1];
+    for (int p = a + 1; p < b; ++p) {
+        const int v = perm[p];
+        int q = p - 1;
+        while (q >= a && perm[q] > v) {
+            perm[q + 1] = perm[q];
+            --q;
+        }
+        perm[q + 1] = v;
+    }
+    for (int p = a; p < b; ++p) rs[p] = rp[perm[p]];
+}
+
+// rs[k].w = P of atom perm[k] (after the density sweep has been finished).
+__global__ __launch_bounds__(256) void k_cell_gather_p(const int *__restrict__ perm, const double4 *__restrict__ xp,
+                                                       double4 *__restrict__ rs, int natoms) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= natoms) return;
+    rs[k] = xp[perm[k]];
+}
+
+// ---------------------------------------------------------------------------
+// Sweeps
+// ---------------------------------------------------------------------------
+template <int W, int PREC, bool GEN, bool FORCE>
+__global__ __launch_bounds__(64 * W) void k_cell_sweep(const CellGrid *__restrict__ grid,
+                                                       const int *__restrict__ cell_cluster,
+                                                       const int *__restrict__ start,
+                                                       const double4 *__restrict__ rs,
+                                                       const int *__restrict__ perm, const int *__restrict__ pslot,
+                                                       double *__restrict__ part, int tile_shift, PotConst pc) {
+    const int cell = blockIdx.x;
+    const int c = cell_cluster[cell];
+    const CellGrid g = grid[c];
+    const int local = cell - g.base;
+    if (local >= g.nx * g.ny * g.nz) return;
+    const int s0 = start[cell], cnt = start[cell + 1] - s0;
+    if (cnt == 0) return;
+    const int ix = local % g.nx, iy = (local / g.nx) % g.ny, iz = local / (g.nx * g.ny);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tile = 1 << tile_shift;
+    const float Af = (float)pc.A;
+    for (int ci = wave * 64; ci < cnt; ci += W * 64) {
+        const bool valid = ci + lane < cnt;
+        const int k = s0 + ci + lane;
+        double xi = -kFar, yi = -kFar, zi = -kFar, ci_ = 0.0;
+        if (valid) {
+            const double4 q = rs[k];
+            xi = q.x;
+            yi = q.y;
+            zi = q.z;
+            ci_ = -q.w;
+        }
+        const float cif = (float)ci_;
+        double acc = 0.0, fx = 0.0, fy = 0.0, fz = 0.0, eu = 0.0;
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int jz = iz + dz;
+            if (jz < 0 || jz >= g.nz) continue;
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int jy = iy + dy;
+                if (jy < 0 || jy >= g.ny) continue;
+                const int row = g.base + (jz * g.ny + jy) * g.nx;
+                const int ja = start[row + max(ix - 1, 0)];
+                const int jb = start[row + min(ix + 1, g.nx - 1) + 1];
+                if (dz == 0 && dy == 0) {
+                    for (int j = ja; j < jb; ++j) {
+                        const double4 q = rs[j];
+                        if constexpr (FORCE) {
+                            force_pair<PREC, GEN, true, true>(xi - q.x, yi - q.y, zi - q.z, j == k, ci_, q.w, cif,
+                                                              (float)q.w, fx, fy, fz, eu, pc, Af);
+                        } else {
+                            density_pair<PREC, GEN, true, true>(xi - q.x, yi - q.y, zi - q.z, j == k, acc, pc);
+                        }
+                    }
+                } else {
+                    for (int j = ja; j < jb; ++j) {
+                        const double4 q = rs[j];
+                        if constexpr (FORCE) {
+                            force_pair<PREC, GEN, false, true>(xi - q.x, yi - q.y, zi - q.z, false, ci_, q.w, cif,
+                                                               (float)q.w, fx, fy, fz, eu, pc, Af);
+                        } else {
+                            density_pair<PREC, GEN, false, true>(xi - q.x, yi - q.y, zi - q.z, false, acc, pc);
+                        }
+                    }
+                }
+            }
+        }
+        if (valid) {
+            const int ps = pslot[perm[k]];
+            if constexpr (FORCE) {
+                const int t = ps >> tile_shift, li = ps & (tile - 1);
+                double *out = part + (size_t)t * 4 * tile + li;
+                out[0] = fx;
+                out[tile] = fy;
+                out[2 * tile] = fz;
+                out[3 * tile] = eu;
+            } else {
+                part[ps] = acc;
+            }
+        }
+    }
+}
+
+constexpr int kCellWaves = 2;
+
+template <bool FORCE>
+hipError_t launch_cell_sweep(CellList *cl, double *part, const PotConst &pc, int precision, hipStream_t s) {
+    (void)hipGetLastError();
+    const dim3 grid(cl->total_cap), block(64 * kCellWaves);
+#define SCMD_CELL_ARGS cl->grid, cl->cell_cluster, cl->start, cl->rs, cl->perm, cl->pslot, part, cl->tile_shift, pc
+    if (precision == SCMD_FP64) {
+        if (pc.generic)
+            hipLaunchKernelGGL((k_cell_sweep<kCellWaves, SCMD_FP64, true, FORCE>), grid, block, 0, s, SCMD_CELL_ARGS);
+        else
+            hipLaunchKernelGGL((k_cell_sweep<kCellWaves, SCMD_FP64, false, FORCE>), grid, block, 0, s, SCMD_CELL_ARGS);
+    } else {
+        if (pc.generic)
+            hipLaunchKernelGGL((k_cell_sweep<kCellWaves, SCMD_MIXED, true, FORCE>), grid, block, 0, s, SCMD_CELL_ARGS);
+        else
+            hipLaunchKernelGGL((k_cell_sweep<kCellWaves, SCMD_MIXED, false, FORCE>), grid, block, 0, s,
+                               SCMD_CELL_ARGS);
+    }
+#undef SCMD_CELL_ARGS
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool cell_list_available() { return true; }
+
+CellList *cell_list_create() {
+    try {
+        return new CellList();
+    } catch (...) {
+        return nullptr;
+    }
+}
+
+void cell_list_destroy(CellList *cl) {
+    if (!cl) return;
+    void *ptrs[] = {cl->grid, cl->cell_cluster, cl->count, cl->start, cl->cursor, cl->cell_of,
+                    cl->perm, cl->pslot, cl->atom_cluster, cl->rs};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete cl;
+}
+
+hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, double rc, const double4 *rp_dev,
+                          const ITile *tiles, int ntiles, int tile) {
+    const int natoms = (int)offsets[nclusters];
+    cl->nclusters = nclusters;
+    cl->natoms = natoms;
+    cl->rc = rc;
+    cl->tile = tile;
+    cl->tile_shift = 0;
+    while ((1 << cl->tile_shift) < tile) ++cl->tile_shift;
+    if ((1 << cl->tile_shift) != tile) return hipErrorInvalidValue;
+    std::vector<double4> r(natoms);
+    hipError_t e;
+    if (natoms > 0 && (e = hipMemcpy(r.data(), rp_dev, natoms * sizeof(double4), hipMemcpyDeviceToHost)) != hipSuccess)
+        return e;
+    // cell capacity per cluster: twice the cells of the initial box per
+    // dimension plus a margin
+    std::vector<CellGrid> grids(nclusters);
+    std::vector<int> cell_cluster;
+    int base = 0;
+    for (int c = 0; c < nclusters; ++c) {
+        CellGrid g{};
+        g.off = (int)offsets[c];
+        g.n = (int)(offsets[c + 1] - offsets[c]);
+        double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int i = g.off; i < g.off + g.n; ++i) {
+            const double v[3] = {r[i].x, r[i].y, r[i].z};
+            for (int d = 0; d < 3; ++d) {
+                if (i == g.off || v[d] < lo[d]) lo[d] = v[d];
+                if (i == g.off || v[d] > hi[d]) hi[d] = v[d];
+            }
+        }
+        int cap[3];
+        for (int d = 0; d < 3; ++d) {
+            const int n0 = (int)std::floor((hi[d] - lo[d]) / rc) + 1;
+            cap[d] = std::min(2 * n0 + 4, 1024);
+        }
+        g.cx = cap[0];
+        g.cy = cap[1];
+        g.cz = cap[2];
+        g.nx = g.ny = g.nz = 1;
+        g.hx = g.hy = g.hz = rc;
+        g.base = base;
+        const int ncap = cap[0] * cap[1] * cap[2];
+        cell_cluster.insert(cell_cluster.end(), ncap, c);
+        base += ncap;
+        grids[c] = g;
+    }
+    cl->total_cap = base;
+    std::vector<int> pslot(natoms), ac(natoms);
+    for (int t = 0; t < ntiles; ++t)
+        for (int li = 0; li < tiles[t].ni; ++li) {
+            pslot[tiles[t].i0 + li] = t * tile + li;
+            ac[tiles[t].i0 + li] = tiles[t].c;
+        }
+    if ((e = dalloc(&cl->grid, nclusters)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->cell_cluster, base)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->count, base)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->start, base + 1)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->cursor, base)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->cell_of, natoms)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->perm, natoms)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->pslot, natoms)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->atom_cluster, natoms)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->rs, natoms)) != hipSuccess) return e;
+    if ((e = hipMemcpy(cl->grid, grids.data(), nclusters * sizeof(CellGrid), hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    if (base > 0 &&
+        (e = hipMemcpy(cl->cell_cluster, cell_cluster.data(), base * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    if (natoms > 0) {
+        if ((e = hipMemcpy(cl->pslot, pslot.data(), natoms * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+            return e;
+        if ((e = hipMemcpy(cl->atom_cluster, ac.data(), natoms * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t cell_list_build(CellList *cl, const double4 *rp, hipStream_t s) {
+    (void)hipGetLastError();
+    const int na = cl->natoms, tc = cl->total_cap;
+    hipLaunchKernelGGL(k_cell_bbox, dim3(cl->nclusters), dim3(kBBoxBlock), 0, s, cl->grid, rp, cl->rc);
+    hipLaunchKernelGGL(k_cell_clear, dim3((tc + 255) / 256), dim3(256), 0, s, cl->count, tc);
+    if (na > 0)
+        hipLaunchKernelGGL(k_cell_count, dim3((na + 255) / 256), dim3(256), 0, s, cl->grid, cl->atom_cluster, rp,
+                           cl->cell_of, cl->count, na);
+    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(kScanBlock), 0, s, cl->count, cl->start, cl->cursor, tc);
+    if (na > 0)
+        hipLaunchKernelGGL(k_cell_scatter, dim3((na + 255) / 256), dim3(256), 0, s, cl->cell_of, cl->cursor, cl->perm,
+                           na);
+    hipLaunchKernelGGL(k_cell_order, dim3((tc + 255) / 256), dim3(256), 0, s, cl->start, cl->perm, rp, cl->rs, tc);
+    return hipGetLastError();
+}
+
+hipError_t cell_list_density(CellList *cl, const SweepBuffers &B, const ITile *tiles, int ntiles, int tile,
+                             const PotConst &pc, int precision, hipStream_t s) {
+    hipError_t e = launch_cell_sweep<false>(cl, B.part, pc, precision, s);
+    if (e != hipSuccess) return e;
+    return launch_density_reduce(tiles, ntiles, tile, B, pc, 1, s);
+}
+
+hipError_t cell_list_force(CellList *cl, const SweepBuffers &B, const StepArgs &a, const ITile *tiles, int ntiles,
+                           int tile, const PotConst &pc, int precision, hipStream_t s) {
+    (void)hipGetLastError();
+    if (cl->natoms > 0)
+        hipLaunchKernelGGL(k_cell_gather_p, dim3((cl->natoms + 255) / 256), dim3(256), 0, s, cl->perm, B.xp, cl->rs,
+                           cl->natoms);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_cell_sweep<true>(cl, B.part, pc, precision, s);
+    if (e != hipSuccess) return e;
+    return launch_force_reduce(tiles, ntiles, tile, B, a, pc, 1, s);
+}
 
 }  // namespace scmd

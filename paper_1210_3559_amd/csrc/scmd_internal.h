@@ -60,10 +60,10 @@ struct ClusterState {
     int32_t pad;
 };
 
-// A pair-sweep work item: atoms [i0, i0+ni) against j in [j0, j1), partial
-// sums written to slot `slot`.
+// A pair-sweep work item: atoms [i0, i0+ni) of tile `tile` against j in
+// [j0, j1), partial sums written to slot `slot`.
 struct SweepItem {
-    int32_t c, i0, ni, j0, j1, slot;
+    int32_t c, i0, ni, j0, j1, slot, tile, pad;
 };
 
 // An atom tile: atoms [i0, i0+ni) of cluster c whose partial sums sit in
@@ -72,30 +72,70 @@ struct ITile {
     int32_t c, i0, ni, first, nsplit, pad;
 };
 
-// Launch helpers implemented in the .hip files.
+// Launch shapes of the all-pairs sweeps: (IPT atoms per lane, WI waves along
+// i, WJ waves along j).  Tile = 64*IPT*WI atoms, block = 64*WI*WJ threads.
+#define SCMD_SWEEP_SHAPES(X) \
+    X(1, 4, 1)               \
+    X(2, 4, 1)               \
+    X(1, 2, 2)               \
+    X(2, 2, 2)               \
+    X(1, 1, 4)               \
+    X(2, 1, 4)               \
+    X(1, 2, 4)               \
+    X(2, 2, 4)               \
+    X(1, 4, 4)               \
+    X(1, 1, 8)               \
+    X(2, 1, 8)               \
+    X(1, 2, 8)               \
+    X(1, 1, 16)              \
+    X(4, 1, 2)               \
+    X(4, 1, 4)               \
+    X(4, 2, 2)
+
 struct SweepLaunch {
     const SweepItem *items;
     const int32_t *order;
+    const ITile *tiles;
     int nitems;
-    int block;   // threads per workgroup
-    int ipt;     // atoms per thread
-    int tile;    // block * ipt
+    int ipt, wi, wj;
 };
 
-hipError_t launch_density(const SweepLaunch &L, const double4 *rp, double *part, const PotConst &pc,
-                          int precision, hipStream_t s);
-hipError_t launch_force(const SweepLaunch &L, const double4 *rp, double *part, const PotConst &pc,
+struct SweepBuffers {
+    const double4 *rp;  // positions (drift output)
+    double4 *xp;        // positions + P (density output, force input)
+    double4 *f;
+    double4 *v;
+    double *rho;
+    double *part;       // partial sums, slot-major
+    double *tile_sums;  // kTileSums doubles per tile
+};
+
+struct StepArgs {
+    const ClusterDesc *cd;
+    ClusterState *st;
+    int *flag;          // non-finite flag
+    double mass_u, dt, h;
+    int advance;        // 1: kick + thermostat (second half of a step); 0: evaluate only
+};
+
+// Pair sweeps.  Tiles whose partner range is one item are finished inside
+// the sweep; when any tile is split (has_split), the matching reduce kernel
+// finishes the split tiles from their partial slots.
+hipError_t launch_density(const SweepLaunch &L, const SweepBuffers &B, const PotConst &pc, int precision,
+                          hipStream_t s);
+hipError_t launch_force(const SweepLaunch &L, const SweepBuffers &B, const StepArgs &a, const PotConst &pc,
                         int precision, hipStream_t s);
+// Reduce kernels finish every tile with at least min_split partial slots
+// (2 after an all-pairs sweep, 1 after a cell-list sweep).
+hipError_t launch_density_reduce(const ITile *tiles, int ntiles, int tile, const SweepBuffers &B,
+                                 const PotConst &pc, int min_split, hipStream_t s);
+hipError_t launch_force_reduce(const ITile *tiles, int ntiles, int tile, const SweepBuffers &B, const StepArgs &a,
+                               const PotConst &pc, int min_split, hipStream_t s);
+// Per-cluster energies, temperature and thermostat factor from the tile sums.
+hipError_t launch_finalize(const StepArgs &a, const double *tile_sums, int nclusters, hipStream_t s);
 
 hipError_t launch_drift(const int32_t *atom_cluster, const ClusterState *st, double4 *rp, double4 *v,
                         const double4 *f, int natoms, double dt, double h, hipStream_t s);
-hipError_t launch_density_reduce(const ITile *tiles, int ntiles, int tile, const double *part, double4 *rp,
-                                 double *rho, double *tile_sums, const PotConst &pc, hipStream_t s);
-hipError_t launch_force_reduce(const ITile *tiles, int ntiles, int tile, const double *part, double4 *f,
-                               double4 *v, double *tile_sums, const PotConst &pc, double h, int kick,
-                               hipStream_t s);
-hipError_t launch_finalize(const ClusterDesc *cd, ClusterState *st, int nclusters, const double *tile_sums,
-                           double mass_u, double dt, int advance, int *flag, hipStream_t s);
 hipError_t launch_aos_from4(const double4 *src, double *dst, int natoms, hipStream_t s);
 
 // Number of doubles per tile in tile_sums: [0] sum e_emb, [1] sum e_pair,

@@ -87,13 +87,15 @@ struct scmd_ctx {
 
     // all-pairs plan
     bool plan_ok = false;
-    int block = 256, ipt = 1, tile = 256;
+    int ipt = 1, wi = 4, wj = 1, tile = 256;
     int nitems = 0, ntiles = 0;
     DevBuf<SweepItem> d_items;
     DevBuf<int32_t> d_order;
     DevBuf<ITile> d_tiles;
     DevBuf<double> d_part;
     DevBuf<double> d_tile_sums;
+    DevBuf<double4> xp;
+    bool has_split = false;  // some tile's partner range spans several items
 
     // cell-list plan (cutoff variant)
     CellList *cells = nullptr;
@@ -108,6 +110,7 @@ struct scmd_ctx {
 
     // profiling
     int profiling = 0;
+    bool capture_sample = false;  // the step being captured carries event nodes
     bool graph_events_ok = true;
     std::vector<EvPair> evs;
     std::vector<int> ev_free, ev_pending, ev_graph;
@@ -218,17 +221,56 @@ void harvest_events(scmd_ctx *c) {
 // -------------------------------------------------------------------------
 // Plan: atom tiles and sweep items
 // -------------------------------------------------------------------------
+// Library default launch shape for the all-pairs sweeps: many short
+// partner loops for small clusters (latency-bound), wide i tiles for large
+// ones (throughput-bound).
+void default_shape(const scmd_ctx *c, int *ipt, int *wi, int *wj, int *target) {
+    int64_t nmax = 0;
+    for (int k = 0; k < c->nclusters; ++k) nmax = std::max<int64_t>(nmax, c->offsets[k + 1] - c->offsets[k]);
+    if (c->nclusters > 1) {  // batches: (2,1,4), fine work splitting
+        *ipt = 2;
+        *wi = 1;
+        *wj = 4;
+        *target = 8192;
+    } else if (nmax <= 4096) {  // small single clusters: latency-bound
+        *ipt = 1;
+        *wi = 1;
+        *wj = 8;
+        *target = 2048;
+    } else {
+        *ipt = 2;
+        *wi = 1;
+        *wj = 8;
+        *target = 2048;
+    }
+}
+
+bool shape_supported(int ipt, int wi, int wj) {
+#define SCMD_SHAPE_OK(I, WI_, WJ_) \
+    if (ipt == I && wi == WI_ && wj == WJ_) return true;
+    SCMD_SWEEP_SHAPES(SCMD_SHAPE_OK)
+#undef SCMD_SHAPE_OK
+    return false;
+}
+
 int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
     c->plan_ok = false;
-    c->block = c->tuning.block > 0 ? c->tuning.block : 256;
-    c->ipt = c->tuning.ipt > 0 ? c->tuning.ipt : 1;
-    if (c->pc.generic) {
-        c->block = 256;
-        c->ipt = 1;
+    int target = 2048;
+    default_shape(c, &c->ipt, &c->wi, &c->wj, &target);
+    if (c->tuning.ipt > 0) {
+        c->ipt = c->tuning.ipt;
+        c->wi = c->tuning.waves_i;
+        c->wj = c->tuning.waves_j;
     }
-    c->tile = c->block * c->ipt;
-    const int target = c->tuning.target_items > 0 ? c->tuning.target_items : 2048;
+    if (c->tuning.target_items > 0) target = c->tuning.target_items;
+    if (c->pc.generic) {  // the generic-exponent kernels exist in one shape
+        c->ipt = 1;
+        c->wi = 4;
+        c->wj = 1;
+    }
+    c->tile = 64 * c->ipt * c->wi;
     const int tile = c->tile;
+    const bool cells = c->neighbour == SCMD_CELLLIST;
     std::vector<ITile> tiles;
     std::vector<SweepItem> items;
     double total = 0.0;
@@ -237,7 +279,7 @@ int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
         const int64_t nt = (n + tile - 1) / tile;
         total += (double)nt * tile * (double)n;
     }
-    const double wstar = std::max(total / target, (double)tile * 64.0);
+    const double wstar = std::max(total / target, (double)tile * 16.0 * c->wj);
     for (int k = 0; k < c->nclusters; ++k) {
         ClusterDesc &d = c->cdesc[k];
         const int off = (int)c->offsets[k];
@@ -247,9 +289,10 @@ int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
         d.tile0 = (int)tiles.size();
         d.ntiles = (n + tile - 1) / tile;
         d.ndof = ndof_of(n);
+        // split the partner range so that each wavefront keeps >= 16 partners
         int nsplit = (int)std::ceil((double)tile * (double)n / wstar);
-        nsplit = std::max(1, std::min(nsplit, std::max(1, n / 64)));
-        if (c->neighbour == SCMD_CELLLIST) nsplit = 1;  // cell sweeps write complete sums
+        nsplit = std::max(1, std::min(nsplit, std::max(1, n / (16 * c->wj))));
+        if (cells) nsplit = 1;  // cell sweeps produce complete sums
         for (int t = 0; t < d.ntiles; ++t) {
             ITile T{};
             T.c = k;
@@ -265,6 +308,7 @@ int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
                 it.j0 = off + (int)((int64_t)n * s / nsplit);
                 it.j1 = off + (int)((int64_t)n * (s + 1) / nsplit);
                 it.slot = (int)items.size();
+                it.tile = (int)tiles.size();
                 items.push_back(it);
             }
             tiles.push_back(T);
@@ -279,12 +323,17 @@ int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
     });
     c->nitems = (int)items.size();
     c->ntiles = (int)tiles.size();
+    c->has_split = false;
+    for (const ITile &T : tiles) c->has_split = c->has_split || T.nsplit > 1;
+    const size_t part_items = cells ? tiles.size() : items.size();
     HIP_TRY(c, c->d_items.ensure(std::max<size_t>(items.size(), 1)));
     HIP_TRY(c, c->d_order.ensure(std::max<size_t>(order.size(), 1)));
     HIP_TRY(c, c->d_tiles.ensure(std::max<size_t>(tiles.size(), 1)));
-    HIP_TRY(c, c->d_part.ensure(std::max<size_t>((size_t)items.size() * 4 * tile, 1)));
+    HIP_TRY(c, c->d_part.ensure(std::max<size_t>(part_items * 4 * (size_t)tile, 1)));
     HIP_TRY(c, c->d_tile_sums.ensure(std::max<size_t>((size_t)tiles.size() * kTileSums, 1)));
     HIP_TRY(c, c->d_cdesc.ensure(std::max<size_t>(c->cdesc.size(), 1)));
+    HIP_TRY(c, c->xp.ensure(std::max<size_t>(c->natoms, 1)));
+    HIP_TRY(c, hipMemset(c->d_tile_sums.p, 0, c->d_tile_sums.n * sizeof(double)));
     if (!items.empty()) {
         HIP_TRY(c, hipMemcpy(c->d_items.p, items.data(), items.size() * sizeof(SweepItem), hipMemcpyHostToDevice));
         HIP_TRY(c, hipMemcpy(c->d_order.p, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -309,8 +358,9 @@ int ensure_plan(scmd_ctx *c) {
     if (c->neighbour == SCMD_CELLLIST) {
         if (!c->cells) c->cells = cell_list_create();
         if (!c->cells) return fail(c, SCMD_ENOMEM, "cell list allocation failed");
-        hipError_t e = cell_list_plan(c->cells, c->nclusters, c->offsets.data(), c->params.rc, tiles.data(),
-                                      c->ntiles, c->tile);
+        hipError_t e = cell_list_plan(c->cells, c->nclusters, c->offsets.data(), c->params.rc, c->rp.p,
+                                      tiles.data(), c->ntiles, c->tile);
+        if (e == hipSuccess) e = hipMemset(c->d_part.p, 0, c->d_part.n * sizeof(double));
         if (e != hipSuccess) return fail(c, SCMD_EDEVICE, std::string("cell list plan: ") + hipGetErrorString(e));
     }
     return SCMD_OK;
@@ -319,52 +369,78 @@ int ensure_plan(scmd_ctx *c) {
 // -------------------------------------------------------------------------
 // Enqueue
 // -------------------------------------------------------------------------
-hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing) {
+// Record event ev on stream s.  During stream capture an event record issued
+// on the stream does not become a graph node on this runtime, so the node is
+// added explicitly after the current capture dependencies.
+hipError_t record(hipEvent_t ev, hipStream_t s, bool capturing) {
+    if (!capturing) return hipEventRecord(ev, s);
+    hipStreamCaptureStatus st;
+    hipGraph_t g = nullptr;
+    const hipGraphNode_t *deps = nullptr;
+    size_t ndeps = 0;
+    hipError_t e = hipStreamGetCaptureInfo_v2(s, &st, nullptr, &g, &deps, &ndeps);
+    if (e != hipSuccess) return e;
+    if (st != hipStreamCaptureStatusActive || !g) return hipErrorIllegalState;
+    hipGraphNode_t node;
+    e = hipGraphAddEventRecordNode(&node, g, deps, ndeps, ev);
+    if (e != hipSuccess) return e;
+    return hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies);
+}
+
+double half_kick(const scmd_ctx *c) { return 0.5 * c->dt / (c->mass * kEvPerUA2Fs2); }
+
+StepArgs step_args(scmd_ctx *c, int advance) {
+    return StepArgs{c->d_cdesc.p, c->d_state.p, c->d_flag.p, c->mass, c->dt, half_kick(c), advance};
+}
+
+SweepBuffers buffers(scmd_ctx *c) {
+    return SweepBuffers{c->rp.p, c->xp.p, c->f.p, c->v.p, c->rho.p, c->d_part.p, c->d_tile_sums.p};
+}
+
+hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int advance) {
     int ev = -1;
-    if (c->profiling && (!capturing || c->graph_events_ok)) {
+    if (c->profiling && (!capturing || (c->graph_events_ok && c->capture_sample))) {
         ev = take_event(c, force ? SCMD_KERNEL_FORCE : SCMD_KERNEL_DENSITY);
         if (ev >= 0) {
-            hipError_t e = hipEventRecord(c->evs[ev].a, s);
+            hipError_t e = record(c->evs[ev].a, s, capturing);
             if (e != hipSuccess) return e;
         }
     }
+    const SweepBuffers B = buffers(c);
+    const StepArgs A = step_args(c, advance);
     hipError_t e;
     if (c->neighbour == SCMD_CELLLIST) {
-        e = force ? cell_list_force(c->cells, c->rp.p, c->d_part.p, c->pc, c->precision, s)
-                  : cell_list_density(c->cells, c->rp.p, c->d_part.p, c->pc, c->precision, s);
+        e = force ? cell_list_force(c->cells, B, A, c->d_tiles.p, c->ntiles, c->tile, c->pc, c->precision, s)
+                  : cell_list_density(c->cells, B, c->d_tiles.p, c->ntiles, c->tile, c->pc, c->precision, s);
     } else {
-        SweepLaunch L{c->d_items.p, c->d_order.p, c->nitems, c->block, c->ipt, c->tile};
-        e = force ? launch_force(L, c->rp.p, c->d_part.p, c->pc, c->precision, s)
-                  : launch_density(L, c->rp.p, c->d_part.p, c->pc, c->precision, s);
+        SweepLaunch L{c->d_items.p, c->d_order.p, c->d_tiles.p, c->nitems, c->ipt, c->wi, c->wj};
+        e = force ? launch_force(L, B, A, c->pc, c->precision, s) : launch_density(L, B, c->pc, c->precision, s);
     }
     if (e != hipSuccess) return e;
     if (ev >= 0) {
-        e = hipEventRecord(c->evs[ev].b, s);
+        e = record(c->evs[ev].b, s, capturing);
         if (e != hipSuccess) return e;
         (capturing ? c->ev_graph : c->ev_pending).push_back(ev);
     }
     return hipSuccess;
 }
 
-double half_kick(const scmd_ctx *c) { return 0.5 * c->dt / (c->mass * kEvPerUA2Fs2); }
-
 // rho, F, energies at the current positions; advance = 1 also kicks and
 // runs the thermostat (second half of a step).
 hipError_t enqueue_forces(scmd_ctx *c, hipStream_t s, bool capturing, int advance) {
     hipError_t e;
+    const SweepBuffers B = buffers(c);
+    const StepArgs A = step_args(c, advance);
     if (c->neighbour == SCMD_CELLLIST) {
         if ((e = cell_list_build(c->cells, c->rp.p, s)) != hipSuccess) return e;
     }
-    if ((e = sweep(c, false, s, capturing)) != hipSuccess) return e;
-    e = launch_density_reduce(c->d_tiles.p, c->ntiles, c->tile, c->d_part.p, c->rp.p, c->rho.p, c->d_tile_sums.p,
-                              c->pc, s);
-    if (e != hipSuccess) return e;
-    if ((e = sweep(c, true, s, capturing)) != hipSuccess) return e;
-    e = launch_force_reduce(c->d_tiles.p, c->ntiles, c->tile, c->d_part.p, c->f.p, c->v.p, c->d_tile_sums.p, c->pc,
-                            half_kick(c), advance, s);
-    if (e != hipSuccess) return e;
-    return launch_finalize(c->d_cdesc.p, c->d_state.p, c->nclusters, c->d_tile_sums.p, c->mass, c->dt, advance,
-                           c->d_flag.p, s);
+    if ((e = sweep(c, false, s, capturing, advance)) != hipSuccess) return e;
+    if (c->has_split && (e = launch_density_reduce(c->d_tiles.p, c->ntiles, c->tile, B, c->pc, 2, s)) != hipSuccess)
+        return e;
+    if ((e = sweep(c, true, s, capturing, advance)) != hipSuccess) return e;
+    if (c->has_split && (e = launch_force_reduce(c->d_tiles.p, c->ntiles, c->tile, B, A, c->pc, 2, s)) != hipSuccess)
+        return e;
+    return launch_finalize(A, c->d_tile_sums.p, c->nclusters, s);
 }
 
 hipError_t enqueue_step(scmd_ctx *c, hipStream_t s, bool capturing) {
@@ -380,7 +456,11 @@ int ensure_graph(scmd_ctx *c) {
     hipGraph_t g = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) e = enqueue_step(c, c->cap_stream, true);
+    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) {
+        c->capture_sample = (k == kGraphSteps - 1);
+        e = enqueue_step(c, c->cap_stream, true);
+    }
+    c->capture_sample = false;
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -422,8 +502,6 @@ int sync_and_check(scmd_ctx *c) {
 int enqueue_steps(scmd_ctx *c, int64_t nsteps) {
     int rc = ensure_plan(c);
     if (rc != SCMD_OK) return rc;
-    if (c->neighbour == SCMD_CELLLIST && cell_list_overflowed(c->cells))
-        return fail(c, SCMD_EBOX, "cell grid exceeded its cap");
     if (!c->have_forces) {
         HIP_TRY(c, enqueue_forces(c, c->stream, false, 0));
         c->have_forces = true;
@@ -482,6 +560,7 @@ void release_device(scmd_ctx *c) {
     c->d_tiles.release();
     c->d_part.release();
     c->d_tile_sums.release();
+    c->xp.release();
     if (c->cells) {
         cell_list_destroy(c->cells);
         c->cells = nullptr;
@@ -520,7 +599,7 @@ const char *scmd_status_string(int status) {
         case SCMD_EDEVICE: return "device or HIP runtime error";
         case SCMD_ENONFINITE: return "non-finite energy";
         case SCMD_ESTATE: return "call out of order";
-        case SCMD_EBOX: return "cell grid cap exceeded";
+        case SCMD_EBOX: return "reserved (cell grid)";
         case SCMD_EUNSUPPORTED: return "unsupported";
         default: return "unknown status";
     }
@@ -767,15 +846,18 @@ int scmd_set_tuning(scmd_ctx *ctx, const scmd_tuning *t) {
     if (!ctx) return SCMD_EINVAL;
     scmd_tuning z{};
     if (t) {
-        if (t->block != 0 && t->block != 64 && t->block != 128 && t->block != 256)
-            return fail(ctx, SCMD_EINVAL, "block must be 64, 128 or 256");
-        if (t->ipt != 0 && t->ipt != 1 && t->ipt != 2 && t->ipt != 4)
-            return fail(ctx, SCMD_EINVAL, "ipt must be 1, 2 or 4");
+        if (t->ipt != 0 || t->waves_i != 0 || t->waves_j != 0) {
+            if (!shape_supported(t->ipt, t->waves_i, t->waves_j))
+                return fail(ctx, SCMD_EINVAL, "unsupported (ipt, waves_i, waves_j) launch shape");
+        }
         if (t->target_items < 0) return fail(ctx, SCMD_EINVAL, "target_items must be >= 0");
         z = *t;
     }
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
     ctx->tuning = z;
     ctx->plan_ok = false;
+    drop_graph(ctx);
     return SCMD_OK;
 }
 
@@ -786,14 +868,9 @@ int scmd_compute(scmd_ctx *ctx) {
         HIP_TRY(ctx, hipSetDevice(ctx->device));
         rc = ensure_plan(ctx);
         if (rc != SCMD_OK) return rc;
-        if (ctx->neighbour == SCMD_CELLLIST && cell_list_overflowed(ctx->cells))
-            return fail(ctx, SCMD_EBOX, "cell grid exceeded its cap");
         HIP_TRY(ctx, enqueue_forces(ctx, ctx->stream, false, 0));
         ctx->have_forces = true;
-        rc = sync_and_check(ctx);
-        if (rc == SCMD_OK && ctx->neighbour == SCMD_CELLLIST && cell_list_overflowed(ctx->cells))
-            return fail(ctx, SCMD_EBOX, "cell grid exceeded its cap");
-        return rc;
+        return sync_and_check(ctx);
     })
 }
 
@@ -816,10 +893,7 @@ int scmd_synchronize(scmd_ctx *ctx) {
             HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
             return SCMD_OK;
         }
-        int rc = sync_and_check(ctx);
-        if (rc == SCMD_OK && ctx->neighbour == SCMD_CELLLIST && ctx->cells && cell_list_overflowed(ctx->cells))
-            return fail(ctx, SCMD_EBOX, "cell grid exceeded its cap");
-        return rc;
+        return sync_and_check(ctx);
     })
 }
 

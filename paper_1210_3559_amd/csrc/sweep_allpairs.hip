@@ -4,157 +4,38 @@
 // first every density rho_i (Sec. 2.1 Eq. (rho)), then the forces, which need
 // psi_j = rho_j^(-1/2) of every partner (Sec. 2 "Computational approach").
 //
-// Work decomposition: an item is an atom tile (BLOCK*IPT atoms, IPT per
-// lane) against a contiguous j chunk of the same cluster.  The j index is
-// uniform across the wavefront, so partner data (x, y, z, P_j packed in one
-// 32-byte double4) is fetched with scalar loads into SGPRs and read directly
-// as a VALU operand: no LDS traffic and no barriers in the inner loop, and
-// each partner fetched once per wave serves 64*IPT pairs from registers.
-// Partial sums go to per-item slots and are reduced in a fixed order by the
-// reduce kernels, so results are deterministic.
+// Work decomposition.  An atom tile holds 64*IPT*WI atoms: WI wavefronts
+// along i, each lane owning IPT atoms.  A work item is one tile against a
+// contiguous j chunk of the same cluster; inside the workgroup the chunk is
+// split again over WJ wavefronts, whose sums are combined in LDS in a fixed
+// order.  The j index is uniform across a wavefront, so partner data
+// (x, y, z[, P_j] packed in a 32-byte double4) comes through scalar loads into
+// SGPRs and is read directly as a VALU operand: no LDS traffic and no barrier
+// in the inner loop, and each partner fetched once per wave serves 64*IPT
+// pairs from registers.
 //
-// Self pairs: the j range is split into the part that overlaps the tile's own
-// atoms (where j == i is masked by pushing r^2 to a huge value, which makes
-// every power term exactly zero) and the parts that do not (no mask at all).
-#include "scmd_internal.h"
-#include "../../include/scmd.h"
+// A tile whose partner range is covered by one item is finished inside the
+// sweep: the density sweep turns sums into rho, psi and the embedding energy,
+// the force sweep stores F and applies the second half-kick, and both write
+// per-tile energy sums.  When a tile's range is split over several items
+// (small clusters, where more parallelism than tiles is needed), each item
+// writes a partial sum to its own slot and a reduce kernel finishes the tile
+// from the slots in slot order.  Kernel boundaries are the only global
+// synchronisation: on gfx950 an agent-scope fence writes back and invalidates
+// the XCD's L2, which costs far more than a launch.  Every reduction has a
+// fixed order, so results are deterministic.
+//
+// Self pairs: the j range of a wavefront is split into the part that
+// overlaps the tile's own atoms (where j == i is voided by pushing r^2 to a
+// huge value, which makes every power term exactly zero) and the parts that
+// do not (no mask at all).
+#include "sweep_common.h"
 
 namespace scmd {
 namespace {
 
-constexpr double kSelfR2 = 1.0e300;
-constexpr float kSelfR2f = 1.0e30f;
+using namespace dev;
 
-// 1/x in double: hardware estimate (about 2^-23 relative) refined by one
-// Newton-Raphson step e = 1 - x y, y += y e (relative error ~ e^2).
-__device__ __forceinline__ double rcp_nr(double x) {
-    double y = __builtin_amdgcn_rcp(x);
-    double e = __builtin_fma(-x, y, 1.0);
-    return __builtin_fma(y, e, y);
-}
-
-// 1/sqrt(x) in double: hardware estimate refined by one Newton-Raphson step
-// y <- y (3/2 - (x/2) y^2) (relative error ~ 1.5 e^2).
-__device__ __forceinline__ double rsq_nr(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    double hx = 0.5 * x;
-    double e = __builtin_fma(-hx, y * y, 1.5);
-    return y * e;
-}
-
-template <typename T>
-__device__ __forceinline__ T powi(T x, int k) {
-    T r = T(1);
-    T b = x;
-    while (k > 0) {
-        if (k & 1) r *= b;
-        b *= b;
-        k >>= 1;
-    }
-    return r;
-}
-
-// ---------------------------------------------------------------------------
-// Density term u^m = (1/r)^m for one pair.
-// ---------------------------------------------------------------------------
-template <int PREC, bool GEN, bool MASK>
-__device__ __forceinline__ void density_pair(double dx, double dy, double dz, bool self, double &acc,
-                                             const PotConst &pc) {
-    if constexpr (PREC == SCMD_FP64) {
-        double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
-        if constexpr (MASK) r2 = self ? kSelfR2 : r2;
-        if constexpr (!GEN) {
-            double w = rcp_nr(r2);           // u^2
-            acc = __builtin_fma(w * w, w, acc);  // + u^6
-        } else {
-            if ((pc.m & 1) == 0) {
-                acc += powi(rcp_nr(r2), pc.m >> 1);
-            } else {
-                acc += powi(rsq_nr(r2), pc.m);
-            }
-        }
-    } else {
-        float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-        float r2 = __builtin_fmaf(fx, fx, __builtin_fmaf(fy, fy, fz * fz));
-        if constexpr (MASK) r2 = self ? kSelfR2f : r2;
-        if constexpr (!GEN) {
-            float w = __builtin_amdgcn_rcpf(r2);
-            acc += (double)(w * w * w);
-        } else {
-            if ((pc.m & 1) == 0) {
-                acc += (double)powi(__builtin_amdgcn_rcpf(r2), pc.m >> 1);
-            } else {
-                acc += (double)powi(__builtin_amdgcn_rsqf(r2), pc.m);
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Force and pair-energy terms for one pair:
-//   F_i += u^(m+2) [A u^(n-m) - P_i - P_j] (r_i - r_j),  eu += u^n.
-// ci = -P_i, pj = P_j.
-// ---------------------------------------------------------------------------
-template <int PREC, bool GEN, bool MASK>
-__device__ __forceinline__ void force_pair(double dx, double dy, double dz, bool self, double ci, double pj,
-                                           float cif, float pjf, double &fx, double &fy, double &fz, double &eu,
-                                           const PotConst &pc, float Af) {
-    if constexpr (PREC == SCMD_FP64) {
-        double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
-        if constexpr (MASK) r2 = self ? kSelfR2 : r2;
-        double u = rsq_nr(r2);
-        double f, un;
-        if constexpr (!GEN) {
-            double u2 = u * u;
-            double u3 = u2 * u;
-            double u4 = u2 * u2;
-            double u8 = u4 * u4;
-            double q = __builtin_fma(pc.A, u3, ci) - pj;
-            f = u8 * q;
-            un = u8 * u;
-        } else {
-            double um2 = powi(u, pc.m + 2);
-            double und = powi(u, pc.n - pc.m);
-            double q = __builtin_fma(pc.A, und, ci) - pj;
-            f = um2 * q;
-            un = powi(u, pc.n);
-        }
-        fx = __builtin_fma(f, dx, fx);
-        fy = __builtin_fma(f, dy, fy);
-        fz = __builtin_fma(f, dz, fz);
-        eu += un;
-    } else {
-        float sx = (float)dx, sy = (float)dy, sz = (float)dz;
-        float r2 = __builtin_fmaf(sx, sx, __builtin_fmaf(sy, sy, sz * sz));
-        if constexpr (MASK) r2 = self ? kSelfR2f : r2;
-        float u = __builtin_amdgcn_rsqf(r2);
-        float f, un;
-        if constexpr (!GEN) {
-            float u2 = u * u;
-            float u3 = u2 * u;
-            float u4 = u2 * u2;
-            float u8 = u4 * u4;
-            float q = __builtin_fmaf(Af, u3, cif) - pjf;
-            f = u8 * q;
-            un = u8 * u;
-        } else {
-            float um2 = powi(u, pc.m + 2);
-            float und = powi(u, pc.n - pc.m);
-            float q = __builtin_fmaf(Af, und, cif) - pjf;
-            f = um2 * q;
-            un = powi(u, pc.n);
-        }
-        double fd = (double)f;
-        fx = __builtin_fma(fd, dx, fx);
-        fy = __builtin_fma(fd, dy, fy);
-        fz = __builtin_fma(fd, dz, fz);
-        eu += (double)un;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// j loops (uniform j: partner data comes through scalar loads)
-// ---------------------------------------------------------------------------
 template <int IPT, int PREC, bool GEN, bool MASK>
 __device__ __forceinline__ void density_range(const double4 *__restrict__ rp, int ja, int jb, const double *xi,
                                               const double *yi, const double *zi, const int *gi, double *acc,
@@ -164,43 +45,65 @@ __device__ __forceinline__ void density_range(const double4 *__restrict__ rp, in
         const double4 q = rp[j];
 #pragma unroll
         for (int p = 0; p < IPT; ++p) {
-            density_pair<PREC, GEN, MASK>(xi[p] - q.x, yi[p] - q.y, zi[p] - q.z, MASK && gi[p] == j, acc[p], pc);
+            density_pair<PREC, GEN, MASK, false>(xi[p] - q.x, yi[p] - q.y, zi[p] - q.z, MASK && gi[p] == j, acc[p],
+                                                 pc);
         }
     }
 }
 
 template <int IPT, int PREC, bool GEN, bool MASK>
-__device__ __forceinline__ void force_range(const double4 *__restrict__ rp, int ja, int jb, const double *xi,
+__device__ __forceinline__ void force_range(const double4 *__restrict__ xp, int ja, int jb, const double *xi,
                                             const double *yi, const double *zi, const double *ci, const float *cif,
                                             const int *gi, double *fx, double *fy, double *fz, double *eu,
                                             const PotConst &pc, float Af) {
 #pragma unroll 2
     for (int j = ja; j < jb; ++j) {
-        const double4 q = rp[j];
+        const double4 q = xp[j];
         const float pjf = PREC == SCMD_FP64 ? 0.0f : (float)q.w;
 #pragma unroll
         for (int p = 0; p < IPT; ++p) {
-            force_pair<PREC, GEN, MASK>(xi[p] - q.x, yi[p] - q.y, zi[p] - q.z, MASK && gi[p] == j, ci[p], q.w,
-                                        cif[p], pjf, fx[p], fy[p], fz[p], eu[p], pc, Af);
+            force_pair<PREC, GEN, MASK, false>(xi[p] - q.x, yi[p] - q.y, zi[p] - q.z, MASK && gi[p] == j, ci[p], q.w,
+                                               cif[p], pjf, fx[p], fy[p], fz[p], eu[p], pc, Af);
         }
     }
 }
 
-// ---------------------------------------------------------------------------
-// Kernels
-// ---------------------------------------------------------------------------
-template <int BLOCK, int IPT, int PREC, bool GEN>
-__global__ __launch_bounds__(BLOCK) void k_density(const SweepItem *__restrict__ items,
-                                                   const int32_t *__restrict__ order,
-                                                   const double4 *__restrict__ rp, double *__restrict__ part,
-                                                   PotConst pc) {
-    constexpr int TILE = BLOCK * IPT;
+// j sub-range of wavefront wj within [j0, j1), split into unmasked / masked /
+// unmasked segments around the tile's own atoms [t0, t1).
+struct Segs {
+    int a, b, c, d;  // [a,b) plain, [b,c) masked, [c,d) plain
+};
+__device__ __forceinline__ Segs segments(int j0, int j1, int wj, int WJ, int t0, int t1) {
+    const int len = j1 - j0;
+    const int ja = j0 + (int)(((int64_t)len * wj) / WJ);
+    const int jb = j0 + (int)(((int64_t)len * (wj + 1)) / WJ);
+    int lo = max(ja, t0), hi = min(jb, t1);
+    if (lo >= hi) lo = hi = jb;
+    return Segs{ja, lo, hi, jb};
+}
+
+template <int IPT, int WI, int WJ, int PREC, bool GEN>
+__global__ __launch_bounds__(64 * WI * WJ) void k_density(const SweepItem *__restrict__ items,
+                                                          const int32_t *__restrict__ order,
+                                                          const ITile *__restrict__ tiles,
+                                                          const double4 *__restrict__ rp, double4 *__restrict__ xp,
+                                                          double *__restrict__ part, double *__restrict__ rho,
+                                                          double *__restrict__ tile_sums, PotConst pc) {
+    constexpr int TILE = 64 * IPT * WI;
+    constexpr int BLOCK = 64 * WI * WJ;
+    __shared__ double sh_x[WJ * TILE];
+    __shared__ double sh_red[BLOCK];
     const SweepItem it = items[order[blockIdx.x]];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wi = wave % WI;
+    const int wj = wave / WI;
+
     double xi[IPT], yi[IPT], zi[IPT], acc[IPT];
     int gi[IPT];
 #pragma unroll
     for (int p = 0; p < IPT; ++p) {
-        const int li = p * BLOCK + (int)threadIdx.x;
+        const int li = wi * 64 * IPT + p * 64 + lane;
         acc[p] = 0.0;
         if (li < it.ni) {
             gi[p] = it.i0 + li;
@@ -213,41 +116,64 @@ __global__ __launch_bounds__(BLOCK) void k_density(const SweepItem *__restrict__
             xi[p] = yi[p] = zi[p] = -kFar;
         }
     }
-    const int lo = max(it.j0, it.i0);
-    const int hi = min(it.j1, it.i0 + it.ni);
-    if (lo < hi) {
-        density_range<IPT, PREC, GEN, false>(rp, it.j0, lo, xi, yi, zi, gi, acc, pc);
-        density_range<IPT, PREC, GEN, true>(rp, lo, hi, xi, yi, zi, gi, acc, pc);
-        density_range<IPT, PREC, GEN, false>(rp, hi, it.j1, xi, yi, zi, gi, acc, pc);
-    } else {
-        density_range<IPT, PREC, GEN, false>(rp, it.j0, it.j1, xi, yi, zi, gi, acc, pc);
-    }
-    double *out = part + (size_t)it.slot * TILE;
+    const Segs sg = segments(it.j0, it.j1, wj, WJ, it.i0, it.i0 + it.ni);
+    density_range<IPT, PREC, GEN, false>(rp, sg.a, sg.b, xi, yi, zi, gi, acc, pc);
+    density_range<IPT, PREC, GEN, true>(rp, sg.b, sg.c, xi, yi, zi, gi, acc, pc);
+    density_range<IPT, PREC, GEN, false>(rp, sg.c, sg.d, xi, yi, zi, gi, acc, pc);
+
+    // combine the WJ wavefronts (fixed order) into sh_x[0 .. TILE)
 #pragma unroll
-    for (int p = 0; p < IPT; ++p) {
-        const int li = p * BLOCK + (int)threadIdx.x;
-        if (li < it.ni) out[li] = acc[p];
+    for (int p = 0; p < IPT; ++p) sh_x[wj * TILE + wi * 64 * IPT + p * 64 + lane] = acc[p];
+    __syncthreads();
+    if (WJ > 1) {
+        for (int li = threadIdx.x; li < TILE; li += BLOCK) {
+            double s = sh_x[li];
+            for (int w = 1; w < WJ; ++w) s += sh_x[w * TILE + li];
+            sh_x[li] = s;
+        }
+        __syncthreads();
     }
+
+    const ITile T = tiles[it.tile];
+    if (T.nsplit > 1) {
+        double *out = part + (size_t)it.slot * TILE;
+        for (int li = threadIdx.x; li < it.ni; li += BLOCK) out[li] = sh_x[li];
+        return;
+    }
+    const DensityOut o{rp, xp, rho, tile_sums};
+    double emb = 0.0;
+    for (int li = threadIdx.x; li < T.ni; li += BLOCK) emb += density_atom(T.i0 + li, sh_x[li], o, pc);
+    emb = block_sum<BLOCK>(emb, sh_red);
+    if (threadIdx.x == 0) tile_sums[(size_t)it.tile * kTileSums + 0] = emb;
 }
 
-template <int BLOCK, int IPT, int PREC, bool GEN>
-__global__ __launch_bounds__(BLOCK) void k_force(const SweepItem *__restrict__ items,
-                                                 const int32_t *__restrict__ order,
-                                                 const double4 *__restrict__ rp, double *__restrict__ part,
-                                                 PotConst pc) {
-    constexpr int TILE = BLOCK * IPT;
+template <int IPT, int WI, int WJ, int PREC, bool GEN>
+__global__ __launch_bounds__(64 * WI * WJ) void k_force(const SweepItem *__restrict__ items,
+                                                        const int32_t *__restrict__ order,
+                                                        const ITile *__restrict__ tiles,
+                                                        const double4 *__restrict__ xp, double *__restrict__ part,
+                                                        ForceOut o, PotConst pc) {
+    constexpr int TILE = 64 * IPT * WI;
+    constexpr int BLOCK = 64 * WI * WJ;
+    __shared__ double sh_x[4 * WJ * TILE];
+    __shared__ double sh_red[BLOCK];
     const SweepItem it = items[order[blockIdx.x]];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wi = wave % WI;
+    const int wj = wave / WI;
     const float Af = (float)pc.A;
+
     double xi[IPT], yi[IPT], zi[IPT], ci[IPT], fx[IPT], fy[IPT], fz[IPT], eu[IPT];
     float cif[IPT];
     int gi[IPT];
 #pragma unroll
     for (int p = 0; p < IPT; ++p) {
-        const int li = p * BLOCK + (int)threadIdx.x;
+        const int li = wi * 64 * IPT + p * 64 + lane;
         fx[p] = fy[p] = fz[p] = eu[p] = 0.0;
         if (li < it.ni) {
             gi[p] = it.i0 + li;
-            const double4 q = rp[gi[p]];
+            const double4 q = xp[gi[p]];
             xi[p] = q.x;
             yi[p] = q.y;
             zi[p] = q.z;
@@ -259,86 +185,236 @@ __global__ __launch_bounds__(BLOCK) void k_force(const SweepItem *__restrict__ i
         }
         cif[p] = (float)ci[p];
     }
-    const int lo = max(it.j0, it.i0);
-    const int hi = min(it.j1, it.i0 + it.ni);
-    if (lo < hi) {
-        force_range<IPT, PREC, GEN, false>(rp, it.j0, lo, xi, yi, zi, ci, cif, gi, fx, fy, fz, eu, pc, Af);
-        force_range<IPT, PREC, GEN, true>(rp, lo, hi, xi, yi, zi, ci, cif, gi, fx, fy, fz, eu, pc, Af);
-        force_range<IPT, PREC, GEN, false>(rp, hi, it.j1, xi, yi, zi, ci, cif, gi, fx, fy, fz, eu, pc, Af);
-    } else {
-        force_range<IPT, PREC, GEN, false>(rp, it.j0, it.j1, xi, yi, zi, ci, cif, gi, fx, fy, fz, eu, pc, Af);
-    }
-    double *out = part + (size_t)it.slot * 4 * TILE;
+    const Segs sg = segments(it.j0, it.j1, wj, WJ, it.i0, it.i0 + it.ni);
+    force_range<IPT, PREC, GEN, false>(xp, sg.a, sg.b, xi, yi, zi, ci, cif, gi, fx, fy, fz, eu, pc, Af);
+    force_range<IPT, PREC, GEN, true>(xp, sg.b, sg.c, xi, yi, zi, ci, cif, gi, fx, fy, fz, eu, pc, Af);
+    force_range<IPT, PREC, GEN, false>(xp, sg.c, sg.d, xi, yi, zi, ci, cif, gi, fx, fy, fz, eu, pc, Af);
+
+    // combine the WJ wavefronts: sh_x[(w*4 + q)*TILE + li]
 #pragma unroll
     for (int p = 0; p < IPT; ++p) {
-        const int li = p * BLOCK + (int)threadIdx.x;
-        if (li < it.ni) {
-            out[li] = fx[p];
-            out[TILE + li] = fy[p];
-            out[2 * TILE + li] = fz[p];
-            out[3 * TILE + li] = eu[p];
+        const int li = wi * 64 * IPT + p * 64 + lane;
+        sh_x[(wj * 4 + 0) * TILE + li] = fx[p];
+        sh_x[(wj * 4 + 1) * TILE + li] = fy[p];
+        sh_x[(wj * 4 + 2) * TILE + li] = fz[p];
+        sh_x[(wj * 4 + 3) * TILE + li] = eu[p];
+    }
+    __syncthreads();
+    if (WJ > 1) {
+        for (int e = threadIdx.x; e < 4 * TILE; e += BLOCK) {
+            double s = sh_x[e];
+            for (int w = 1; w < WJ; ++w) s += sh_x[w * 4 * TILE + e];
+            sh_x[e] = s;
         }
+        __syncthreads();
+    }
+
+    const ITile T = tiles[it.tile];
+    if (T.nsplit > 1) {
+        double *out = part + (size_t)it.slot * 4 * TILE;
+        for (int e = threadIdx.x; e < 4 * TILE; e += BLOCK)
+            if ((e % TILE) < it.ni) out[e] = sh_x[e];
+        return;
+    }
+    double epair = 0.0, v2 = 0.0;
+    for (int li = threadIdx.x; li < T.ni; li += BLOCK)
+        force_atom(T.i0 + li, sh_x[li], sh_x[TILE + li], sh_x[2 * TILE + li], sh_x[3 * TILE + li], o, pc, epair,
+                   v2);
+    epair = block_sum<BLOCK>(epair, sh_red);
+    v2 = block_sum<BLOCK>(v2, sh_red);
+    if (threadIdx.x == 0) {
+        o.tile_sums[(size_t)it.tile * kTileSums + 1] = epair;
+        o.tile_sums[(size_t)it.tile * kTileSums + 2] = v2;
     }
 }
 
-template <int BLOCK, int IPT, int PREC, bool GEN>
-hipError_t launch_shape(bool force, const SweepLaunch &L, const double4 *rp, double *part, const PotConst &pc,
-                        hipStream_t s) {
-    if (L.nitems <= 0) return hipSuccess;
-    if (force) {
-        hipLaunchKernelGGL((k_force<BLOCK, IPT, PREC, GEN>), dim3(L.nitems), dim3(BLOCK), 0, s, L.items, L.order,
-                           rp, part, pc);
+// ---------------------------------------------------------------------------
+// Reduce kernels for split tiles: one workgroup of 256 threads per tile; G =
+// 256 / TILE thread groups each sum every G-th slot (in order), then the
+// group sums are added in group order.
+// ---------------------------------------------------------------------------
+constexpr int kRedBlock = 256;
+
+template <int TILE, int Q>
+__device__ __forceinline__ void reduce_slots(const ITile &T, const double *__restrict__ part, double *sh) {
+    constexpr int G = TILE < kRedBlock ? kRedBlock / TILE : 1;
+    const int t = threadIdx.x;
+    if (G > 1) {
+        const int li = t % TILE, g = t / TILE;
+        if (li < T.ni) {
+            double s[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) s[q] = 0.0;
+            for (int k = g; k < T.nsplit; k += G) {
+                const double *p = part + ((size_t)(T.first + k) * Q) * TILE + li;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) s[q] += p[(size_t)q * TILE];
+            }
+#pragma unroll
+            for (int q = 0; q < Q; ++q) sh[(g * Q + q) * TILE + li] = s[q];
+        }
+        __syncthreads();
+        if (t < TILE && t < T.ni) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                double s = sh[q * TILE + t];
+                for (int gg = 1; gg < G; ++gg) s += sh[(gg * Q + q) * TILE + t];
+                sh[q * TILE + t] = s;
+            }
+        }
+        __syncthreads();
     } else {
-        hipLaunchKernelGGL((k_density<BLOCK, IPT, PREC, GEN>), dim3(L.nitems), dim3(BLOCK), 0, s, L.items,
-                           L.order, rp, part, pc);
+        for (int li = t; li < T.ni; li += kRedBlock) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                sh[q * TILE + li] = sum_slots(part + ((size_t)T.first * Q + q) * TILE + li, T.nsplit, (size_t)Q * TILE);
+        }
+        __syncthreads();
+    }
+}
+
+template <int TILE>
+__global__ __launch_bounds__(kRedBlock) void k_density_reduce(const ITile *__restrict__ tiles,
+                                                              const double *__restrict__ part, DensityOut o,
+                                                              PotConst pc, int min_split) {
+    constexpr int G = TILE < kRedBlock ? kRedBlock / TILE : 1;
+    __shared__ double sh[G * TILE];
+    __shared__ double sh_red[kRedBlock];
+    const ITile T = tiles[blockIdx.x];
+    if (T.nsplit < min_split) return;
+    reduce_slots<TILE, 1>(T, part, sh);
+    double emb = 0.0;
+    for (int li = threadIdx.x; li < T.ni; li += kRedBlock) emb += density_atom(T.i0 + li, sh[li], o, pc);
+    emb = block_sum<kRedBlock>(emb, sh_red);
+    if (threadIdx.x == 0) o.tile_sums[(size_t)blockIdx.x * kTileSums + 0] = emb;
+}
+
+template <int TILE>
+__global__ __launch_bounds__(kRedBlock) void k_force_reduce(const ITile *__restrict__ tiles,
+                                                            const double *__restrict__ part, ForceOut o,
+                                                            PotConst pc, int min_split) {
+    constexpr int G = TILE < kRedBlock ? kRedBlock / TILE : 1;
+    __shared__ double sh[4 * G * TILE];
+    __shared__ double sh_red[kRedBlock];
+    const ITile T = tiles[blockIdx.x];
+    if (T.nsplit < min_split) return;
+    reduce_slots<TILE, 4>(T, part, sh);
+    double epair = 0.0, v2 = 0.0;
+    for (int li = threadIdx.x; li < T.ni; li += kRedBlock)
+        force_atom(T.i0 + li, sh[li], sh[TILE + li], sh[2 * TILE + li], sh[3 * TILE + li], o, pc, epair, v2);
+    epair = block_sum<kRedBlock>(epair, sh_red);
+    v2 = block_sum<kRedBlock>(v2, sh_red);
+    if (threadIdx.x == 0) {
+        o.tile_sums[(size_t)blockIdx.x * kTileSums + 1] = epair;
+        o.tile_sums[(size_t)blockIdx.x * kTileSums + 2] = v2;
+    }
+}
+
+constexpr int kFinBlock = 256;
+
+__global__ __launch_bounds__(kFinBlock) void k_finalize(FinalizeArgs a) {
+    __shared__ double sh[kFinBlock];
+    cluster_finalize<kFinBlock>(blockIdx.x, a, sh);
+}
+
+template <int IPT, int WI, int WJ, int PREC, bool GEN>
+hipError_t launch_shape(bool force, const SweepLaunch &L, const SweepBuffers &B, const ForceOut &o,
+                        const PotConst &pc, hipStream_t s) {
+    constexpr int BLOCK = 64 * WI * WJ;
+    if (L.nitems <= 0) return hipSuccess;
+    (void)hipGetLastError();
+    if (force) {
+        hipLaunchKernelGGL((k_force<IPT, WI, WJ, PREC, GEN>), dim3(L.nitems), dim3(BLOCK), 0, s, L.items, L.order,
+                           L.tiles, B.xp, B.part, o, pc);
+    } else {
+        hipLaunchKernelGGL((k_density<IPT, WI, WJ, PREC, GEN>), dim3(L.nitems), dim3(BLOCK), 0, s, L.items, L.order,
+                           L.tiles, B.rp, B.xp, B.part, B.rho, B.tile_sums, pc);
     }
     return hipGetLastError();
 }
 
 template <int PREC, bool GEN>
-hipError_t dispatch_shape(bool force, const SweepLaunch &L, const double4 *rp, double *part, const PotConst &pc,
-                          hipStream_t s) {
+hipError_t dispatch_shape(bool force, const SweepLaunch &L, const SweepBuffers &B, const ForceOut &o,
+                          const PotConst &pc, hipStream_t s) {
+#define SCMD_SHAPE(I, WI_, WJ_)                                 \
+    if (L.ipt == I && L.wi == WI_ && L.wj == WJ_)               \
+        return launch_shape<I, WI_, WJ_, PREC, GEN>(force, L, B, o, pc, s);
     if constexpr (GEN) {
         // the generic-exponent path exists in one launch shape only
-        if (L.block == 256 && L.ipt == 1) return launch_shape<256, 1, PREC, true>(force, L, rp, part, pc, s);
-        return hipErrorInvalidValue;
+        SCMD_SHAPE(1, 4, 1)
     } else {
-#define SCMD_SHAPE(B, I) \
-    if (L.block == B && L.ipt == I) return launch_shape<B, I, PREC, false>(force, L, rp, part, pc, s);
-        SCMD_SHAPE(64, 1)
-        SCMD_SHAPE(64, 2)
-        SCMD_SHAPE(64, 4)
-        SCMD_SHAPE(128, 1)
-        SCMD_SHAPE(128, 2)
-        SCMD_SHAPE(128, 4)
-        SCMD_SHAPE(256, 1)
-        SCMD_SHAPE(256, 2)
-        SCMD_SHAPE(256, 4)
+        SCMD_SWEEP_SHAPES(SCMD_SHAPE)
+    }
 #undef SCMD_SHAPE
-        return hipErrorInvalidValue;
-    }
-}
-
-hipError_t dispatch(bool force, const SweepLaunch &L, const double4 *rp, double *part, const PotConst &pc,
-                    int precision, hipStream_t s) {
-    if (precision == SCMD_FP64) {
-        return pc.generic ? dispatch_shape<SCMD_FP64, true>(force, L, rp, part, pc, s)
-                          : dispatch_shape<SCMD_FP64, false>(force, L, rp, part, pc, s);
-    }
-    return pc.generic ? dispatch_shape<SCMD_MIXED, true>(force, L, rp, part, pc, s)
-                      : dispatch_shape<SCMD_MIXED, false>(force, L, rp, part, pc, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t launch_density(const SweepLaunch &L, const double4 *rp, double *part, const PotConst &pc, int precision,
+hipError_t launch_density(const SweepLaunch &L, const SweepBuffers &B, const PotConst &pc, int precision,
                           hipStream_t s) {
-    return dispatch(false, L, rp, part, pc, precision, s);
+    ForceOut o{};
+    if (precision == SCMD_FP64)
+        return pc.generic ? dispatch_shape<SCMD_FP64, true>(false, L, B, o, pc, s)
+                          : dispatch_shape<SCMD_FP64, false>(false, L, B, o, pc, s);
+    return pc.generic ? dispatch_shape<SCMD_MIXED, true>(false, L, B, o, pc, s)
+                      : dispatch_shape<SCMD_MIXED, false>(false, L, B, o, pc, s);
 }
 
-hipError_t launch_force(const SweepLaunch &L, const double4 *rp, double *part, const PotConst &pc, int precision,
-                        hipStream_t s) {
-    return dispatch(true, L, rp, part, pc, precision, s);
+hipError_t launch_force(const SweepLaunch &L, const SweepBuffers &B, const StepArgs &a, const PotConst &pc,
+                        int precision, hipStream_t s) {
+    ForceOut o{B.f, B.v, B.tile_sums, a.h, a.advance};
+    if (precision == SCMD_FP64)
+        return pc.generic ? dispatch_shape<SCMD_FP64, true>(true, L, B, o, pc, s)
+                          : dispatch_shape<SCMD_FP64, false>(true, L, B, o, pc, s);
+    return pc.generic ? dispatch_shape<SCMD_MIXED, true>(true, L, B, o, pc, s)
+                      : dispatch_shape<SCMD_MIXED, false>(true, L, B, o, pc, s);
+}
+
+template <int TILE>
+static hipError_t reduce_tile(bool force, const ITile *tiles, int ntiles, const SweepBuffers &B, const ForceOut &fo,
+                              const PotConst &pc, int min_split, hipStream_t s) {
+    (void)hipGetLastError();
+    if (force) {
+        hipLaunchKernelGGL((k_force_reduce<TILE>), dim3(ntiles), dim3(kRedBlock), 0, s, tiles, B.part, fo, pc,
+                           min_split);
+    } else {
+        const DensityOut o{B.rp, B.xp, B.rho, B.tile_sums};
+        hipLaunchKernelGGL((k_density_reduce<TILE>), dim3(ntiles), dim3(kRedBlock), 0, s, tiles, B.part, o, pc,
+                           min_split);
+    }
+    return hipGetLastError();
+}
+
+static hipError_t reduce_dispatch(bool force, const ITile *tiles, int ntiles, int tile, const SweepBuffers &B,
+                                  const ForceOut &fo, const PotConst &pc, int min_split, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    switch (tile) {
+        case 64: return reduce_tile<64>(force, tiles, ntiles, B, fo, pc, min_split, s);
+        case 128: return reduce_tile<128>(force, tiles, ntiles, B, fo, pc, min_split, s);
+        case 256: return reduce_tile<256>(force, tiles, ntiles, B, fo, pc, min_split, s);
+        case 512: return reduce_tile<512>(force, tiles, ntiles, B, fo, pc, min_split, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_density_reduce(const ITile *tiles, int ntiles, int tile, const SweepBuffers &B,
+                                 const PotConst &pc, int min_split, hipStream_t s) {
+    return reduce_dispatch(false, tiles, ntiles, tile, B, ForceOut{}, pc, min_split, s);
+}
+
+hipError_t launch_force_reduce(const ITile *tiles, int ntiles, int tile, const SweepBuffers &B, const StepArgs &a,
+                               const PotConst &pc, int min_split, hipStream_t s) {
+    const ForceOut fo{B.f, B.v, B.tile_sums, a.h, a.advance};
+    return reduce_dispatch(true, tiles, ntiles, tile, B, fo, pc, min_split, s);
+}
+
+hipError_t launch_finalize(const StepArgs &a, const double *tile_sums, int nclusters, hipStream_t s) {
+    if (nclusters <= 0) return hipSuccess;
+    const FinalizeArgs fa{a.cd, a.st, tile_sums, a.flag, a.mass_u, a.dt, a.advance};
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_finalize, dim3(nclusters), dim3(kFinBlock), 0, s, fa);
+    return hipGetLastError();
 }
 
 }  // namespace scmd

@@ -277,3 +277,35 @@ def concat(workloads) -> Workload:
     th = sum((list(w.thermostat) for w in workloads), [])
     return Workload("+".join(w.name for w in workloads), np.ascontiguousarray(pos), np.ascontiguousarray(vel),
                     offsets, workloads[0].dt, max(w.steps for w in workloads), th)
+
+
+def by_name(name: str) -> Workload:
+    """Named workloads of the benchmark and the autotuner."""
+    if name == "ni2243_cooling":
+        return c2_cooling()
+    if name == "ni147_nve":
+        return c1_icosahedron()
+    if name == "ni48077_allpairs":
+        return c3_large()
+    if name == "ni48077_cell":
+        return c3_large(cutoff=True)
+    if name == "ni15000_mixed":
+        return c4_mixed()
+    if name == "ni15000_fp64":
+        w = c4_mixed()
+        w.precision = "fp64"
+        w.name = "ni15000_fcc_nve_fp64"
+        return w
+    if name == "batch256":
+        return c5_batch()
+    if name == "batch256_mixed":
+        w = c5_batch()
+        w.precision = "mixed"
+        w.name += "_mixed"
+        return w
+    if name == "ni50000_allpairs":
+        pos = jitter(fcc_exact(50000), 0.05, np.random.default_rng(50000))
+        vel = maxwell_boltzmann(pos, 1900.0, np.random.default_rng(50001))
+        th = dict(T_start=1900.0, T_end=1900.0, ramp_steps=0, tau=100.0)
+        return _single("ni50000_fcc_nvt_allpairs", pos, vel, 1.0, 10_000, th)
+    raise KeyError(f"unknown workload {name}")

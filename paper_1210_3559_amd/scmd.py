@@ -62,8 +62,8 @@ class _Params(ctypes.Structure):
 
 
 class _Tuning(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int), ("ipt", ctypes.c_int), ("target_items", ctypes.c_int),
-                ("reserved", ctypes.c_int)]
+    _fields_ = [("ipt", ctypes.c_int), ("waves_i", ctypes.c_int), ("waves_j", ctypes.c_int),
+                ("target_items", ctypes.c_int)]
 
 
 _lib = None
@@ -189,8 +189,8 @@ def scmd_set_thermostat(ctx, cluster: int, kind: int, T_start_K: float = 0.0, T_
                                            int(ramp_steps), float(tau_fs)))
 
 
-def scmd_set_tuning(ctx, block: int = 0, ipt: int = 0, target_items: int = 0) -> None:
-    t = _Tuning(int(block), int(ipt), int(target_items), 0)
+def scmd_set_tuning(ctx, ipt: int = 0, waves_i: int = 0, waves_j: int = 0, target_items: int = 0) -> None:
+    t = _Tuning(int(ipt), int(waves_i), int(waves_j), int(target_items))
     _check(ctx, load().scmd_set_tuning(ctx, ctypes.byref(t)))
 
 
@@ -312,6 +312,9 @@ class Simulation:
             scmd_set_potential(self.ctx, **p)
             scmd_set_integrator(self.ctx, dt, PRECISIONS[precision],
                                 SCMD_CELLLIST if p["rc"] > 0 else SCMD_ALLPAIRS)
+            if tuning == "auto":
+                from . import autotune
+                tuning = autotune.lookup(offsets, precision)
             if tuning:
                 scmd_set_tuning(self.ctx, **tuning)
             for k, th in enumerate(thermostats or []):

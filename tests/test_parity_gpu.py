@@ -78,10 +78,26 @@ def test_compute_parity_c2_start():
     check_single(inputs.c2_cooling().pos)
 
 
-@pytest.mark.parametrize("block,ipt", [(64, 1), (64, 2), (64, 4), (128, 1), (128, 2), (128, 4), (256, 1),
-                                       (256, 2), (256, 4)])
-def test_compute_parity_launch_shapes(block, ipt):
-    check_single(_cluster(1337, seed=5), tuning=dict(block=block, ipt=ipt, target_items=97))
+SHAPES = [(1, 4, 1), (2, 4, 1), (1, 2, 2), (2, 2, 2), (1, 1, 4), (2, 1, 4), (1, 2, 4), (2, 2, 4), (1, 4, 4),
+          (1, 1, 8), (2, 1, 8), (1, 2, 8), (1, 1, 16), (4, 1, 2), (4, 1, 4), (4, 2, 2)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("target", [0, 97])
+def test_compute_parity_launch_shapes(shape, target):
+    ipt, wi, wj = shape
+    check_single(_cluster(1337, seed=5), tuning=dict(ipt=ipt, waves_i=wi, waves_j=wj, target_items=target))
+
+
+def test_step_parity_across_launch_shapes():
+    # a few steps per shape: arrival counters and kicks stay consistent
+    w = inputs.c2_cooling()
+    r_ref, v_ref, _, _ = oracle.vv_run(w.pos, w.vel, 5, dt=w.dt, thermostat=w.thermostat[0], nthreads=NT)
+    for ipt, wi, wj in SHAPES:
+        with scmd.Simulation.from_workload(w, tuning=dict(ipt=ipt, waves_i=wi, waves_j=wj)) as sim:
+            sim.step(5)
+            assert np.abs(sim.positions() - r_ref).max() < 1e-11, (ipt, wi, wj)
+            assert np.abs(sim.velocities() - v_ref).max() < 1e-12, (ipt, wi, wj)
 
 
 @pytest.mark.parametrize("n", [147, 777, 2243])
@@ -317,3 +333,80 @@ def test_profiling_records_sweep_times():
     print(f"[prof] force {ms_f:.4f} ms x{n_f}, density {ms_d:.4f} ms x{n_d}", flush=True)
     assert n_f >= 5 and n_d >= 5
     assert 0.0 < ms_f < 100.0 and 0.0 < ms_d < 100.0
+
+
+# --------------------------------------------------------------------------
+# Cell-list variant (truncated, shifted potential) against the brute-force
+# cutoff oracle
+# --------------------------------------------------------------------------
+RC = 8.8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("n", [1, 2, 13, 64, 500, 2243])
+def test_cell_list_compute_parity(n, precision):
+    pos = inputs.c2_cooling().pos if n == 2243 else _cluster(n, seed=100 + n, amp=0.2)
+    check_single(pos, precision=precision, params=dict(rc=RC))
+
+
+def test_cell_list_batch_with_escaped_atom():
+    # an atom that leaves its cluster after the grid was planned stretches the
+    # box beyond the cell capacity: cells coarsen, results stay exact
+    a = _cluster(300, seed=7, amp=0.2)
+    b = _cluster(200, seed=8, amp=0.2) + 500.0
+    offsets = np.array([0, 300, 300, 500], dtype=np.int64)
+    pos = np.concatenate([a, b])
+    vel = np.zeros_like(pos)
+    vel[17] = [70.0, 0.0, 0.0]  # A/fs
+    with scmd.Simulation(offsets, pos, vel, dt=1.0, rc=RC) as sim:
+        sim.step(12)
+        r = sim.positions()
+        sim.compute()
+        f, rho = sim.forces(), sim.density()
+        ens = [sim.energy(k) for k in range(3)]
+    assert r[17, 0] > 700.0
+    for k in (0, 2):
+        lo, hi = offsets[k], offsets[k + 1]
+        f_ref, rho_ref, site = oracle.forces(r[lo:hi], params=dict(rc=RC), nthreads=NT)
+        assert_forces_close(f[lo:hi], f_ref, 1e-10)
+        np.testing.assert_allclose(rho[lo:hi], rho_ref, rtol=1e-10, atol=0)
+        assert ens[k][0] == pytest.approx(site.sum(), rel=1e-10)
+    assert ens[1] == (0.0, 0.0, 0.0)
+    assert rho[17] == 0.0 and np.all(f[17] == 0.0)
+
+
+def test_cell_list_trajectory_parity():
+    w = inputs.c2_cooling()
+    th = dict(T_start=2000.0, T_end=800.0, ramp_steps=50, tau=100.0)
+    print("[traj] Ni2243 cell list 80 steps", flush=True)
+    r_ref, v_ref, _, log = oracle.vv_run(w.pos, w.vel, 80, dt=2.0, thermostat=th, params=dict(rc=RC), nthreads=NT)
+    with scmd.Simulation(w.offsets, w.pos, w.vel, dt=2.0, rc=RC, thermostats=[th]) as sim:
+        sim.step(80)
+        r, v = sim.positions(), sim.velocities()
+        ep, ek, _ = sim.energy(0)
+    assert np.abs(r - r_ref).max() < 1e-9
+    assert np.abs(v - v_ref).max() < 1e-10
+    assert ep == pytest.approx(log[79, 0], rel=1e-10)
+    assert ek == pytest.approx(log[79, 1], rel=1e-9)
+
+
+def test_cell_list_full_size_48k_sampled():
+    w = inputs.c3_large(cutoff=True)
+    print(f"[parity] cell list n={w.n_atoms}", flush=True)
+    f, rho, ens = run_compute(w.offsets, w.pos, params=dict(rc=RC))
+    idx = np.random.default_rng(3).choice(w.n_atoms, 48, replace=False)
+    f_ref, rho_ref = oracle.forces_subset(w.pos, idx, params=dict(rc=RC), nthreads=NT)
+    np.testing.assert_allclose(rho, rho_ref, rtol=1e-10)
+    frms = np.sqrt(np.mean(np.sum(f ** 2, axis=1)))
+    per = np.linalg.norm(f[idx] - f_ref, axis=1)
+    assert np.all(per <= 1e-10 * np.maximum(np.linalg.norm(f_ref, axis=1), frms))
+
+
+def test_cell_list_is_deterministic():
+    w = inputs.c2_cooling()
+    outs = []
+    for _ in range(2):
+        with scmd.Simulation(w.offsets, w.pos, w.vel, dt=2.0, rc=RC) as sim:
+            sim.step(40)
+            outs.append(sim.positions())
+    np.testing.assert_array_equal(outs[0], outs[1])
