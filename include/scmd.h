@@ -117,6 +117,11 @@ typedef struct {
     int waves_i;
     int waves_j;
     int target_items;
+    int pairs; /* 0 = library choice; 1 = one-sided sweeps (every atom owns its
+                  sums, shapes above); 2 = symmetric sweeps (each unordered
+                  pair evaluated once, j tiles rotated through the wavefront;
+                  ipt 2 or 4, waves_i and waves_j ignored; (n, m) = (9, 6) and
+                  all-pairs only) */
 } scmd_tuning;
 
 /* Kernel classes timed by scmd_get_kernel_time (device time per launch). */

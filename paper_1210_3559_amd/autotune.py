@@ -40,14 +40,18 @@ def _time(sim: "scmd.Simulation", steps: int) -> float:
     return (time.perf_counter() - t0) / steps
 
 
-def tune(w, precision: str | None = None, budget_s: float = 0.25, shapes=SHAPES, targets=TARGETS, verbose=True):
+def tune(w, precision: str | None = None, budget_s: float = 0.25, shapes=SHAPES, targets=TARGETS, verbose=True,
+         symmetric: bool = True):
     """Time every shape/target on workload w; returns (best tuning dict, table)."""
     precision = precision or w.precision
     pairs = float(np.sum(w.sizes().astype(np.float64) ** 2))
     table = []
-    for ipt, wi, wj in shapes:
+    candidates = [dict(ipt=ipt, waves_i=wi, waves_j=wj, pairs=1) for ipt, wi, wj in shapes]
+    if symmetric:
+        candidates += [dict(ipt=ipt, pairs=2) for ipt in (2, 4)]
+    for cand in candidates:
         for tgt in targets:
-            tun = dict(ipt=ipt, waves_i=wi, waves_j=wj, target_items=tgt)
+            tun = dict(cand, target_items=tgt)
             with scmd.Simulation.from_workload(w, precision=precision, tuning=tun) as sim:
                 sim.step(32)
                 dt1 = _time(sim, 32)

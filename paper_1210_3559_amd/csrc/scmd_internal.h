@@ -131,6 +131,35 @@ hipError_t launch_density_reduce(const ITile *tiles, int ntiles, int tile, const
                                  const PotConst &pc, int min_split, hipStream_t s);
 hipError_t launch_force_reduce(const ITile *tiles, int ntiles, int tile, const SweepBuffers &B, const StepArgs &a,
                                const PotConst &pc, int min_split, hipStream_t s);
+// Symmetric (each unordered pair once) all-pairs sweeps.  Tiles are 64
+// atoms; IPT consecutive tiles of a cluster form a group held by one
+// wavefront.  An item is a group against the later tiles [b0, b1) (global
+// tile indices), or the group's own pairs when b0 == b1.
+struct SymItem {
+    int32_t c, g, t0, ng, b0, b1, slot, pad;  // g: group index within the cluster; t0: its first tile
+};
+// A 64-atom tile: its j-side partials sit at jbase + g for the nj groups
+// before it; its i-side partials are items [item0, item0 + nitems) at lane
+// block p of each item.
+struct SymTile {
+    int32_t c, i0, ni, jbase, nj, item0, nitems, p;
+};
+struct SymLaunch {
+    const SymItem *items;
+    const int32_t *order;
+    const SymTile *tiles;
+    int nitems, ntiles, ipt;
+    double *ipart;  // nitems x 4 x 64*IPT
+    double *jpart;  // sum(nj) x 3 x 64
+};
+// stage 0: the sweep (partials); stage 1: reduce + tile finish (density:
+// rho, P, embedding sums; force: F, kick, pair-energy and v^2 sums).  FP64
+// or mixed; (n, m) = (9, 6) and no cutoff only.
+hipError_t launch_sym_density(const SymLaunch &L, const SweepBuffers &B, const PotConst &pc, int precision,
+                              int stage, hipStream_t s);
+hipError_t launch_sym_force(const SymLaunch &L, const SweepBuffers &B, const StepArgs &a, const PotConst &pc,
+                            int precision, int stage, hipStream_t s);
+
 // Per-cluster energies, temperature and thermostat factor from the tile sums.
 hipError_t launch_finalize(const StepArgs &a, const double *tile_sums, int nclusters, hipStream_t s);
 

@@ -97,6 +97,14 @@ struct scmd_ctx {
     DevBuf<double4> xp;
     bool has_split = false;  // some tile's partner range spans several items
 
+    // symmetric all-pairs plan
+    bool sym = false;
+    int sym_ipt = 4, sym_nitems = 0, sym_ntiles = 0;
+    DevBuf<SymItem> d_sitems;
+    DevBuf<int32_t> d_sorder;
+    DevBuf<SymTile> d_stiles;
+    DevBuf<double> d_ipart, d_jpart;
+
     // cell-list plan (cutoff variant)
     CellList *cells = nullptr;
 
@@ -253,8 +261,108 @@ bool shape_supported(int ipt, int wi, int wj) {
     return false;
 }
 
+// Symmetric plan: 64-atom tiles, groups of IPT tiles, one diagonal item per
+// group and the group's later tiles cut into chunks of about equal work.
+int build_sym_plan(scmd_ctx *c, int target) {
+    const int ipt = c->sym_ipt;
+    std::vector<SymTile> tiles;
+    std::vector<SymItem> items;
+    double offdiag = 0.0;
+    for (int k = 0; k < c->nclusters; ++k) {
+        const int64_t n = c->offsets[k + 1] - c->offsets[k];
+        const int64_t nt = (n + 63) / 64;
+        for (int64_t g = 0; g * ipt < nt; ++g) offdiag += (double)std::max<int64_t>(0, nt - (g + 1) * ipt);
+    }
+    const int chunk = std::max(1, (int)std::ceil(offdiag / std::max(1, target)));
+    int jbase = 0;
+    for (int k = 0; k < c->nclusters; ++k) {
+        ClusterDesc &d = c->cdesc[k];
+        const int off = (int)c->offsets[k];
+        const int n = (int)(c->offsets[k + 1] - c->offsets[k]);
+        const int nt = (n + 63) / 64;
+        d.off = off;
+        d.n = n;
+        d.tile0 = (int)tiles.size();
+        d.ntiles = nt;
+        d.ndof = ndof_of(n);
+        for (int t = 0; t < nt; ++t) {
+            SymTile T{};
+            T.c = k;
+            T.i0 = off + 64 * t;
+            T.ni = std::min(64, n - 64 * t);
+            T.nj = t / ipt;
+            T.jbase = jbase;
+            T.p = t % ipt;
+            jbase += T.nj;
+            tiles.push_back(T);
+        }
+        for (int g = 0; g * ipt < nt; ++g) {
+            const int first = (int)items.size();
+            SymItem it{};
+            it.c = k;
+            it.g = g;
+            it.t0 = d.tile0 + g * ipt;
+            it.ng = std::min(ipt, nt - g * ipt);
+            it.b0 = it.b1 = 0;
+            it.slot = first;
+            items.push_back(it);
+            for (int b = (g + 1) * ipt; b < nt; b += chunk) {
+                SymItem o = it;
+                o.b0 = d.tile0 + b;
+                o.b1 = d.tile0 + std::min(nt, b + chunk);
+                o.slot = (int)items.size();
+                items.push_back(o);
+            }
+            for (int t = g * ipt; t < g * ipt + it.ng; ++t) {
+                tiles[d.tile0 + t].item0 = first;
+                tiles[d.tile0 + t].nitems = (int)items.size() - first;
+            }
+        }
+    }
+    std::vector<int32_t> order(items.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+    auto work = [&](const SymItem &it) -> int64_t {
+        return it.b1 > it.b0 ? (int64_t)(it.b1 - it.b0) * 64 * 64 * it.ng : (int64_t)64 * 64 * it.ng * it.ng / 2;
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return work(items[x]) > work(items[y]); });
+    c->sym_nitems = (int)items.size();
+    c->sym_ntiles = (int)tiles.size();
+    c->ntiles = (int)tiles.size();
+    HIP_TRY(c, c->d_sitems.ensure(std::max<size_t>(items.size(), 1)));
+    HIP_TRY(c, c->d_sorder.ensure(std::max<size_t>(order.size(), 1)));
+    HIP_TRY(c, c->d_stiles.ensure(std::max<size_t>(tiles.size(), 1)));
+    HIP_TRY(c, c->d_ipart.ensure(std::max<size_t>(items.size() * 4 * 64 * (size_t)ipt, 1)));
+    HIP_TRY(c, c->d_jpart.ensure(std::max<size_t>((size_t)jbase * 3 * 64, 1)));
+    HIP_TRY(c, c->d_tile_sums.ensure(std::max<size_t>((size_t)tiles.size() * kTileSums, 1)));
+    HIP_TRY(c, c->d_cdesc.ensure(std::max<size_t>(c->cdesc.size(), 1)));
+    HIP_TRY(c, c->xp.ensure(std::max<size_t>(c->natoms, 1)));
+    HIP_TRY(c, hipMemset(c->d_tile_sums.p, 0, c->d_tile_sums.n * sizeof(double)));
+    if (!items.empty()) {
+        HIP_TRY(c, hipMemcpy(c->d_sitems.p, items.data(), items.size() * sizeof(SymItem), hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->d_sorder.p, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    if (!tiles.empty())
+        HIP_TRY(c, hipMemcpy(c->d_stiles.p, tiles.data(), tiles.size() * sizeof(SymTile), hipMemcpyHostToDevice));
+    if (!c->cdesc.empty())
+        HIP_TRY(c, hipMemcpy(c->d_cdesc.p, c->cdesc.data(), c->cdesc.size() * sizeof(ClusterDesc),
+                             hipMemcpyHostToDevice));
+    c->plan_ok = true;
+    return SCMD_OK;
+}
+
 int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
     c->plan_ok = false;
+    {
+        int64_t nmax = 0;
+        for (int k = 0; k < c->nclusters; ++k) nmax = std::max<int64_t>(nmax, c->offsets[k + 1] - c->offsets[k]);
+        const bool allowed = c->neighbour == SCMD_ALLPAIRS && !c->pc.generic;
+        c->sym = allowed && (c->tuning.pairs == 2 || (c->tuning.pairs == 0 && nmax >= 8192));
+        if (c->sym) {
+            c->sym_ipt = (c->tuning.ipt == 2 || c->tuning.ipt == 4) ? c->tuning.ipt : 4;
+            return build_sym_plan(c, c->tuning.target_items > 0 ? c->tuning.target_items : 4096);
+        }
+    }
     int target = 2048;
     default_shape(c, &c->ipt, &c->wi, &c->wj, &target);
     if (c->tuning.ipt > 0) {
@@ -409,7 +517,12 @@ hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int adv
     const SweepBuffers B = buffers(c);
     const StepArgs A = step_args(c, advance);
     hipError_t e;
-    if (c->neighbour == SCMD_CELLLIST) {
+    if (c->sym) {
+        const SymLaunch L{c->d_sitems.p, c->d_sorder.p, c->d_stiles.p, c->sym_nitems, c->sym_ntiles, c->sym_ipt,
+                          c->d_ipart.p, c->d_jpart.p};
+        e = force ? launch_sym_force(L, B, A, c->pc, c->precision, 0, s)
+                  : launch_sym_density(L, B, c->pc, c->precision, 0, s);
+    } else if (c->neighbour == SCMD_CELLLIST) {
         e = force ? cell_list_force(c->cells, B, A, c->d_tiles.p, c->ntiles, c->tile, c->pc, c->precision, s)
                   : cell_list_density(c->cells, B, c->d_tiles.p, c->ntiles, c->tile, c->pc, c->precision, s);
     } else {
@@ -431,6 +544,15 @@ hipError_t enqueue_forces(scmd_ctx *c, hipStream_t s, bool capturing, int advanc
     hipError_t e;
     const SweepBuffers B = buffers(c);
     const StepArgs A = step_args(c, advance);
+    if (c->sym) {
+        const SymLaunch L{c->d_sitems.p, c->d_sorder.p, c->d_stiles.p, c->sym_nitems, c->sym_ntiles, c->sym_ipt,
+                          c->d_ipart.p, c->d_jpart.p};
+        if ((e = sweep(c, false, s, capturing, advance)) != hipSuccess) return e;
+        if ((e = launch_sym_density(L, B, c->pc, c->precision, 1, s)) != hipSuccess) return e;
+        if ((e = sweep(c, true, s, capturing, advance)) != hipSuccess) return e;
+        if ((e = launch_sym_force(L, B, A, c->pc, c->precision, 1, s)) != hipSuccess) return e;
+        return launch_finalize(A, c->d_tile_sums.p, c->nclusters, s);
+    }
     if (c->neighbour == SCMD_CELLLIST) {
         if ((e = cell_list_build(c->cells, c->rp.p, s)) != hipSuccess) return e;
     }
@@ -561,6 +683,11 @@ void release_device(scmd_ctx *c) {
     c->d_part.release();
     c->d_tile_sums.release();
     c->xp.release();
+    c->d_sitems.release();
+    c->d_sorder.release();
+    c->d_stiles.release();
+    c->d_ipart.release();
+    c->d_jpart.release();
     if (c->cells) {
         cell_list_destroy(c->cells);
         c->cells = nullptr;
@@ -846,11 +973,15 @@ int scmd_set_tuning(scmd_ctx *ctx, const scmd_tuning *t) {
     if (!ctx) return SCMD_EINVAL;
     scmd_tuning z{};
     if (t) {
-        if (t->ipt != 0 || t->waves_i != 0 || t->waves_j != 0) {
+        if (t->pairs == 2) {
+            if (t->ipt != 0 && t->ipt != 2 && t->ipt != 4)
+                return fail(ctx, SCMD_EINVAL, "symmetric sweeps take ipt 2 or 4");
+        } else if (t->ipt != 0 || t->waves_i != 0 || t->waves_j != 0) {
             if (!shape_supported(t->ipt, t->waves_i, t->waves_j))
                 return fail(ctx, SCMD_EINVAL, "unsupported (ipt, waves_i, waves_j) launch shape");
         }
         if (t->target_items < 0) return fail(ctx, SCMD_EINVAL, "target_items must be >= 0");
+        if (t->pairs < 0 || t->pairs > 2) return fail(ctx, SCMD_EINVAL, "pairs must be 0, 1 or 2");
         z = *t;
     }
     (void)hipSetDevice(ctx->device);

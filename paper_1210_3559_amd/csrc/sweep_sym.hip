@@ -1,0 +1,379 @@
+// Symmetric (Newton's third law) all-pairs sweeps for large clusters.
+//
+// Both sweeps of the paper's scheme (Sec. 2.1 Eqs. (SC), (rho); Sec. 2
+// "Computational approach") are symmetric in i and j: (a/r_ij)^m enters
+// rho_i and rho_j alike, and the force term of a pair acts with opposite
+// signs on i and j.  Here every unordered pair is evaluated once.
+//
+// Atoms of a cluster are cut into 64-atom tiles; IPT consecutive tiles form
+// a group that sits in one wavefront (lane l owns atom l of each of the
+// group's tiles).  A work item is one group against a run of later tiles:
+// each j tile is loaded one atom per lane and then rotated through the
+// wavefront with DPP wave_ror:1 64 times, so that every lane meets every j
+// atom; the j tile carries its own force (or density) accumulators along.
+// Pairs inside a group are done one-sidedly by a separate diagonal item.
+//
+// Outputs are partial sums: the i side per item, the j side per (group,
+// tile).  The reduce kernels add, for every atom, its group's i-side items in
+// item order and then the j-side partials of every earlier group in group
+// order: the result is deterministic.  Pair energy: each unordered pair adds
+// 2 u^n to the i side (diagonal items add u^n per ordered pair), so
+// E_pair = (eps/2) a^n sum over all atoms, as in the one-sided sweeps.
+#include "sweep_common.h"
+
+namespace scmd {
+namespace {
+
+using namespace dev;
+
+// Lane l receives the value of lane l-1 (mod 64): DPP wave_ror:1.  Every
+// source lane is valid, so no "old" value is needed (bound_ctrl set).
+__device__ __forceinline__ double ror1(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x13C, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x13C, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// i atoms of the group held by this lane.
+template <int IPT>
+struct IGroup {
+    double x[IPT], y[IPT], z[IPT], c[IPT];  // c = -P_i
+    int gi[IPT];
+};
+
+template <int IPT>
+__device__ __forceinline__ void load_group(const SymItem &it, const SymTile *__restrict__ tiles,
+                                           const double4 *__restrict__ src, IGroup<IPT> &G) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int p = 0; p < IPT; ++p) {
+        G.gi[p] = -1;
+        G.x[p] = G.y[p] = G.z[p] = -kFar;
+        G.c[p] = 0.0;
+        if (p < it.ng) {
+            const SymTile t = tiles[it.t0 + p];
+            if (lane < t.ni) {
+                G.gi[p] = t.i0 + lane;
+                const double4 q = src[G.gi[p]];
+                G.x[p] = q.x;
+                G.y[p] = q.y;
+                G.z[p] = q.z;
+                G.c[p] = -q.w;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Force sweep
+// ---------------------------------------------------------------------------
+template <int PREC>
+__device__ __forceinline__ void sym_force_pair(double dx, double dy, double dz, double ci, double pj, float cif,
+                                               float pjf, double &fx, double &fy, double &fz, double &eu,
+                                               double &gx, double &gy, double &gz, const PotConst &pc, float Af) {
+    double f, un;
+    if constexpr (PREC == SCMD_FP64) {
+        const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
+        const double u = rsq_nr(r2);
+        const double u2 = u * u;
+        const double u3 = u2 * u;
+        const double u4 = u2 * u2;
+        const double u8 = u4 * u4;
+        const double q = __builtin_fma(pc.A, u3, ci) - pj;
+        f = u8 * q;
+        un = u8 * u;
+    } else {
+        const double r2d = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
+        const float u = __builtin_amdgcn_rsqf((float)r2d);
+        const float u2 = u * u;
+        const float u3 = u2 * u;
+        const float u4 = u2 * u2;
+        const float u8 = u4 * u4;
+        const float q = __builtin_fmaf(Af, u3, cif) - pjf;
+        f = (double)(u8 * q);
+        un = (double)(u8 * u);
+    }
+    fx = __builtin_fma(f, dx, fx);
+    fy = __builtin_fma(f, dy, fy);
+    fz = __builtin_fma(f, dz, fz);
+    gx = __builtin_fma(-f, dx, gx);
+    gy = __builtin_fma(-f, dy, gy);
+    gz = __builtin_fma(-f, dz, gz);
+    eu += un;
+}
+
+template <int IPT, int PREC>
+__global__ __launch_bounds__(64) void k_sym_force(const SymItem *__restrict__ items, const int32_t *__restrict__ order,
+                                                  const SymTile *__restrict__ tiles, const double4 *__restrict__ xp,
+                                                  double *__restrict__ ipart, double *__restrict__ jpart,
+                                                  PotConst pc) {
+    const SymItem it = items[order[blockIdx.x]];
+    const int lane = threadIdx.x & 63;
+    const float Af = (float)pc.A;
+    IGroup<IPT> G;
+    load_group<IPT>(it, tiles, xp, G);
+    float cif[IPT];
+    double fx[IPT], fy[IPT], fz[IPT], eu[IPT];
+#pragma unroll
+    for (int p = 0; p < IPT; ++p) {
+        fx[p] = fy[p] = fz[p] = eu[p] = 0.0;
+        cif[p] = (float)G.c[p];
+    }
+    if (it.b0 == it.b1) {
+        // diagonal item: every ordered pair inside the group, one-sided
+        const SymTile first = tiles[it.t0];
+        const SymTile last = tiles[it.t0 + it.ng - 1];
+        const int ja = first.i0, jb = last.i0 + last.ni;
+        for (int j = ja; j < jb; ++j) {
+            const double4 q = xp[j];
+            const float pjf = (float)q.w;
+#pragma unroll
+            for (int p = 0; p < IPT; ++p) {
+                force_pair<PREC, false, true, false>(G.x[p] - q.x, G.y[p] - q.y, G.z[p] - q.z, G.gi[p] == j, G.c[p],
+                                                     q.w, cif[p], pjf, fx[p], fy[p], fz[p], eu[p], pc, Af);
+            }
+        }
+    } else {
+        for (int b = it.b0; b < it.b1; ++b) {
+            const SymTile t = tiles[b];
+            double xj = kFar, yj = kFar, zj = kFar, pj = 0.0;
+            if (lane < t.ni) {
+                const double4 q = xp[t.i0 + lane];
+                xj = q.x;
+                yj = q.y;
+                zj = q.z;
+                pj = q.w;
+            }
+            double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll 2
+            for (int k = 0; k < 64; ++k) {
+                const float pjf = (float)pj;
+#pragma unroll
+                for (int p = 0; p < IPT; ++p) {
+                    sym_force_pair<PREC>(G.x[p] - xj, G.y[p] - yj, G.z[p] - zj, G.c[p], pj, cif[p], pjf, fx[p], fy[p],
+                                         fz[p], eu[p], gx, gy, gz, pc, Af);
+                }
+                xj = ror1(xj);
+                yj = ror1(yj);
+                zj = ror1(zj);
+                pj = ror1(pj);
+                gx = ror1(gx);
+                gy = ror1(gy);
+                gz = ror1(gz);
+            }
+            double *out = jpart + ((size_t)(t.jbase + it.g) * 3) * 64 + lane;
+            out[0] = gx;
+            out[64] = gy;
+            out[128] = gz;
+        }
+#pragma unroll
+        for (int p = 0; p < IPT; ++p) eu[p] *= 2.0;  // each unordered pair once
+    }
+    double *out = ipart + (size_t)it.slot * 4 * 64 * IPT;
+#pragma unroll
+    for (int p = 0; p < IPT; ++p) {
+        out[(0 * IPT + p) * 64 + lane] = fx[p];
+        out[(1 * IPT + p) * 64 + lane] = fy[p];
+        out[(2 * IPT + p) * 64 + lane] = fz[p];
+        out[(3 * IPT + p) * 64 + lane] = eu[p];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Density sweep
+// ---------------------------------------------------------------------------
+template <int IPT, int PREC>
+__global__ __launch_bounds__(64) void k_sym_density(const SymItem *__restrict__ items,
+                                                    const int32_t *__restrict__ order,
+                                                    const SymTile *__restrict__ tiles, const double4 *__restrict__ rp,
+                                                    double *__restrict__ ipart, double *__restrict__ jpart,
+                                                    PotConst pc) {
+    const SymItem it = items[order[blockIdx.x]];
+    const int lane = threadIdx.x & 63;
+    IGroup<IPT> G;
+    load_group<IPT>(it, tiles, rp, G);
+    double acc[IPT];
+#pragma unroll
+    for (int p = 0; p < IPT; ++p) acc[p] = 0.0;
+    if (it.b0 == it.b1) {
+        const SymTile first = tiles[it.t0];
+        const SymTile last = tiles[it.t0 + it.ng - 1];
+        const int ja = first.i0, jb = last.i0 + last.ni;
+        for (int j = ja; j < jb; ++j) {
+            const double4 q = rp[j];
+#pragma unroll
+            for (int p = 0; p < IPT; ++p)
+                density_pair<PREC, false, true, false>(G.x[p] - q.x, G.y[p] - q.y, G.z[p] - q.z, G.gi[p] == j, acc[p],
+                                                       pc);
+        }
+    } else {
+        for (int b = it.b0; b < it.b1; ++b) {
+            const SymTile t = tiles[b];
+            double xj = kFar, yj = kFar, zj = kFar;
+            if (lane < t.ni) {
+                const double4 q = rp[t.i0 + lane];
+                xj = q.x;
+                yj = q.y;
+                zj = q.z;
+            }
+            double rj = 0.0;
+#pragma unroll 2
+            for (int k = 0; k < 64; ++k) {
+#pragma unroll
+                for (int p = 0; p < IPT; ++p) {
+                    const double dx = G.x[p] - xj, dy = G.y[p] - yj, dz = G.z[p] - zj;
+                    double t6;
+                    if constexpr (PREC == SCMD_FP64) {
+                        const double w = rcp_nr(__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)));
+                        t6 = w * w * w;
+                    } else {
+                        const float w = __builtin_amdgcn_rcpf((float)__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)));
+                        t6 = (double)(w * w * w);
+                    }
+                    acc[p] += t6;
+                    rj += t6;
+                }
+                xj = ror1(xj);
+                yj = ror1(yj);
+                zj = ror1(zj);
+                rj = ror1(rj);
+            }
+            jpart[(size_t)(t.jbase + it.g) * 64 + lane] = rj;
+        }
+    }
+    double *out = ipart + (size_t)it.slot * 64 * IPT;
+#pragma unroll
+    for (int p = 0; p < IPT; ++p) out[p * 64 + lane] = acc[p];
+}
+
+// ---------------------------------------------------------------------------
+// Reduce + finish: one workgroup of 256 threads per 64-atom tile.  Thread
+// (g4, lane): g4 = 0..3 interleaves the j-side partials; i-side items are
+// summed by g4 == 0.  Group sums are combined in g4 order.
+// ---------------------------------------------------------------------------
+constexpr int kSymRed = 256;
+
+template <int IPT, int Q>
+__device__ __forceinline__ void sym_sums(const SymTile &t, const double *__restrict__ ipart,
+                                         const double *__restrict__ jpart, double *sh) {
+    const int lane = threadIdx.x & 63, g4 = threadIdx.x >> 6;
+    double s[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s[q] = 0.0;
+    if (lane < t.ni) {
+        if (g4 == 0) {
+            for (int k = 0; k < t.nitems; ++k) {
+                const double *p = ipart + (size_t)(t.item0 + k) * Q * 64 * IPT + t.p * 64 + lane;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) s[q] += p[(size_t)q * IPT * 64];
+            }
+        }
+        constexpr int QJ = Q == 4 ? 3 : 1;  // the j side carries no energy
+        for (int g = g4; g < t.nj; g += 4) {
+            const double *p = jpart + ((size_t)(t.jbase + g) * QJ) * 64 + lane;
+#pragma unroll
+            for (int q = 0; q < QJ; ++q) s[q] += p[q * 64];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) sh[(g4 * Q + q) * 64 + lane] = s[q];
+    __syncthreads();
+    if (g4 == 0) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            double v = sh[q * 64 + lane];
+            for (int gg = 1; gg < 4; ++gg) v += sh[(gg * Q + q) * 64 + lane];
+            sh[q * 64 + lane] = v;
+        }
+    }
+    __syncthreads();
+}
+
+template <int IPT>
+__global__ __launch_bounds__(kSymRed) void k_sym_density_reduce(const SymTile *__restrict__ tiles,
+                                                                const double *__restrict__ ipart,
+                                                                const double *__restrict__ jpart, DensityOut o,
+                                                                PotConst pc) {
+    __shared__ double sh[4 * 64];
+    __shared__ double sh_red[kSymRed];
+    const SymTile t = tiles[blockIdx.x];
+    sym_sums<IPT, 1>(t, ipart, jpart, sh);
+    double emb = 0.0;
+    if (threadIdx.x < t.ni) emb = density_atom(t.i0 + threadIdx.x, sh[threadIdx.x], o, pc);
+    emb = block_sum<kSymRed>(emb, sh_red);
+    if (threadIdx.x == 0) o.tile_sums[(size_t)blockIdx.x * kTileSums + 0] = emb;
+}
+
+template <int IPT>
+__global__ __launch_bounds__(kSymRed) void k_sym_force_reduce(const SymTile *__restrict__ tiles,
+                                                              const double *__restrict__ ipart,
+                                                              const double *__restrict__ jpart, ForceOut o,
+                                                              PotConst pc) {
+    __shared__ double sh[4 * 4 * 64];
+    __shared__ double sh_red[kSymRed];
+    const SymTile t = tiles[blockIdx.x];
+    sym_sums<IPT, 4>(t, ipart, jpart, sh);
+    double epair = 0.0, v2 = 0.0;
+    const int l = threadIdx.x;
+    if (l < t.ni) force_atom(t.i0 + l, sh[l], sh[64 + l], sh[128 + l], sh[192 + l], o, pc, epair, v2);
+    epair = block_sum<kSymRed>(epair, sh_red);
+    v2 = block_sum<kSymRed>(v2, sh_red);
+    if (threadIdx.x == 0) {
+        o.tile_sums[(size_t)blockIdx.x * kTileSums + 1] = epair;
+        o.tile_sums[(size_t)blockIdx.x * kTileSums + 2] = v2;
+    }
+}
+
+template <int IPT, int PREC>
+hipError_t launch_ipt(bool force, int stage, const SymLaunch &L, const SweepBuffers &B, const ForceOut &fo,
+                      const PotConst &pc, hipStream_t s) {
+    (void)hipGetLastError();
+    if (stage == 0 && L.nitems > 0) {
+        if (force)
+            hipLaunchKernelGGL((k_sym_force<IPT, PREC>), dim3(L.nitems), dim3(64), 0, s, L.items, L.order, L.tiles,
+                               B.xp, L.ipart, L.jpart, pc);
+        else
+            hipLaunchKernelGGL((k_sym_density<IPT, PREC>), dim3(L.nitems), dim3(64), 0, s, L.items, L.order, L.tiles,
+                               B.rp, L.ipart, L.jpart, pc);
+    }
+    if (stage == 1 && L.ntiles > 0) {
+        if (force) {
+            hipLaunchKernelGGL((k_sym_force_reduce<IPT>), dim3(L.ntiles), dim3(kSymRed), 0, s, L.tiles, L.ipart,
+                               L.jpart, fo, pc);
+        } else {
+            const DensityOut o{B.rp, B.xp, B.rho, B.tile_sums};
+            hipLaunchKernelGGL((k_sym_density_reduce<IPT>), dim3(L.ntiles), dim3(kSymRed), 0, s, L.tiles, L.ipart,
+                               L.jpart, o, pc);
+        }
+    }
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t dispatch_ipt(bool force, int stage, const SymLaunch &L, const SweepBuffers &B, const ForceOut &fo,
+                        const PotConst &pc, hipStream_t s) {
+    switch (L.ipt) {
+        case 2: return launch_ipt<2, PREC>(force, stage, L, B, fo, pc, s);
+        case 4: return launch_ipt<4, PREC>(force, stage, L, B, fo, pc, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sym_density(const SymLaunch &L, const SweepBuffers &B, const PotConst &pc, int precision,
+                              int stage, hipStream_t s) {
+    if (pc.generic || pc.cut) return hipErrorInvalidValue;
+    return precision == SCMD_FP64 ? dispatch_ipt<SCMD_FP64>(false, stage, L, B, ForceOut{}, pc, s)
+                                  : dispatch_ipt<SCMD_MIXED>(false, stage, L, B, ForceOut{}, pc, s);
+}
+
+hipError_t launch_sym_force(const SymLaunch &L, const SweepBuffers &B, const StepArgs &a, const PotConst &pc,
+                            int precision, int stage, hipStream_t s) {
+    if (pc.generic || pc.cut) return hipErrorInvalidValue;
+    const ForceOut fo{B.f, B.v, B.tile_sums, a.h, a.advance};
+    return precision == SCMD_FP64 ? dispatch_ipt<SCMD_FP64>(true, stage, L, B, fo, pc, s)
+                                  : dispatch_ipt<SCMD_MIXED>(true, stage, L, B, fo, pc, s);
+}
+
+}  // namespace scmd

@@ -63,7 +63,7 @@ class _Params(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("ipt", ctypes.c_int), ("waves_i", ctypes.c_int), ("waves_j", ctypes.c_int),
-                ("target_items", ctypes.c_int)]
+                ("target_items", ctypes.c_int), ("pairs", ctypes.c_int)]
 
 
 _lib = None
@@ -189,8 +189,9 @@ def scmd_set_thermostat(ctx, cluster: int, kind: int, T_start_K: float = 0.0, T_
                                            int(ramp_steps), float(tau_fs)))
 
 
-def scmd_set_tuning(ctx, ipt: int = 0, waves_i: int = 0, waves_j: int = 0, target_items: int = 0) -> None:
-    t = _Tuning(int(ipt), int(waves_i), int(waves_j), int(target_items))
+def scmd_set_tuning(ctx, ipt: int = 0, waves_i: int = 0, waves_j: int = 0, target_items: int = 0,
+                    pairs: int = 0) -> None:
+    t = _Tuning(int(ipt), int(waves_i), int(waves_j), int(target_items), int(pairs))
     _check(ctx, load().scmd_set_tuning(ctx, ctypes.byref(t)))
 
 

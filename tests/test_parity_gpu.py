@@ -410,3 +410,52 @@ def test_cell_list_is_deterministic():
             sim.step(40)
             outs.append(sim.positions())
     np.testing.assert_array_equal(outs[0], outs[1])
+
+
+# --------------------------------------------------------------------------
+# Symmetric sweeps (each unordered pair once, j tiles rotated by DPP)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("ipt", [2, 4])
+@pytest.mark.parametrize("n", [2, 64, 65, 300, 1000, 2243, 4097])
+def test_symmetric_compute_parity(n, ipt):
+    pos = inputs.c2_cooling().pos if n == 2243 else _cluster(n, seed=200 + n)
+    check_single(pos, tuning=dict(pairs=2, ipt=ipt, target_items=61))
+
+
+@pytest.mark.parametrize("n", [300, 2243])
+def test_symmetric_compute_parity_mixed(n):
+    check_single(_cluster(n, seed=9), precision="mixed", tuning=dict(pairs=2, ipt=4))
+
+
+def test_symmetric_batch_parity():
+    sizes = [147, 0, 1, 2, 333, 64, 1000, 5, 129]
+    parts = [_cluster(s, seed=30 + k, amp=0.1) for k, s in enumerate(sizes)]
+    pos = np.concatenate(parts)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    with scmd.Simulation(offsets, pos, None, tuning=dict(pairs=2, ipt=2, target_items=33)) as sim:
+        sim.compute()
+        f, rho = sim.forces(), sim.density()
+        ens = [sim.energy(k) for k in range(len(sizes))]
+    for k, p in enumerate(parts):
+        a, b = offsets[k], offsets[k + 1]
+        if b == a:
+            continue
+        f_ref, rho_ref, site = oracle.forces(p, nthreads=NT)
+        assert_forces_close(f[a:b], f_ref, 1e-10)
+        np.testing.assert_allclose(rho[a:b], rho_ref, rtol=1e-10)
+        assert ens[k][0] == pytest.approx(site.sum(), rel=1e-10)
+
+
+def test_symmetric_trajectory_parity_and_determinism():
+    w = inputs.c2_cooling()
+    th = w.thermostat[0]
+    r_ref, v_ref, _, log = oracle.vv_run(w.pos, w.vel, 40, dt=w.dt, thermostat=th, nthreads=NT)
+    outs = []
+    for _ in range(2):
+        with scmd.Simulation.from_workload(w, tuning=dict(pairs=2, ipt=4)) as sim:
+            sim.step(40)
+            outs.append((sim.positions(), sim.velocities(), sim.energy()))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    assert np.abs(outs[0][0] - r_ref).max() < 1e-10
+    assert np.abs(outs[0][1] - v_ref).max() < 1e-11
+    assert outs[0][2][0] == pytest.approx(log[39, 0], rel=1e-10)
