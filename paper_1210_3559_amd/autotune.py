@@ -23,7 +23,7 @@ from . import scmd
 
 SHAPES = [(1, 4, 1), (2, 4, 1), (1, 2, 2), (2, 2, 2), (1, 1, 4), (2, 1, 4), (1, 2, 4), (2, 2, 4), (1, 4, 4),
           (1, 1, 8), (2, 1, 8), (1, 2, 8), (1, 1, 16), (4, 1, 2), (4, 1, 4), (4, 2, 2)]
-TARGETS = [512, 2048, 8192]
+TARGETS = [1, 512, 2048, 8192]
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 ARCH = "gfx950"
 

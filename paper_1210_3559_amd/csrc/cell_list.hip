@@ -6,19 +6,20 @@
 // r < rc through a cell list rebuilt every step.
 //
 // Build (every step, every cluster independently, free boundaries):
-//   bbox    one workgroup per cluster: bounding box of its atoms; cells are
-//           boxes of edge h >= rc over it (h grows beyond rc only if the box
-//           would need more cells than the cluster's cell capacity, so an
-//           escaping atom makes cells coarser, never wrong);
+//   bbox    per chunk of 4096 atoms of a cluster: min/max, merged per
+//           cluster with 64-bit integer atomics on an order-preserving
+//           encoding (exact, so the order does not matter);
+//   grid    per cluster: cells of edge h >= rc over the box (h grows beyond
+//           rc only if the box would need more cells than the cluster's cell
+//           capacity, so an escaping atom makes cells coarser, never wrong);
 //   count   per atom: its cell, integer atomics count atoms per cell;
 //   scan    exclusive prefix sum of the counts (one workgroup);
 //   scatter per atom: a slot in its cell (atomic cursor);
-//   order   per cell: the slots sorted by atom index, so the cell-sorted
-//           order is deterministic; sorted positions are gathered.
-// Sweeps: one workgroup per cell; its atoms are the lanes (64 per wavefront,
-// chunks beyond that), and the partners are the atoms of the 27 neighbouring
-// cells, read as 9 contiguous x-rows of the sorted arrays with wave-uniform
-// scalar loads.  Every atom's sum is complete after one sweep, so the tiles
+//   order   per cell: every atom's slot becomes its rank by atom index, so
+//           the cell-sorted order is deterministic; positions are gathered.
+// Sweeps: one workgroup per cell; its atoms are the lanes (64 at a time),
+// three wavefronts split the 27 neighbouring cells, read as 9 contiguous
+// x-rows of the sorted arrays with wave-uniform scalar loads.  Every atom's sum is complete after one sweep, so the tiles
 // of the all-pairs plan are finished by the same reduce kernels with one
 // slot per tile.
 #include <algorithm>
@@ -49,7 +50,11 @@ struct CellList {
     int *start = nullptr;         // [total_cap + 1]
     int *cursor = nullptr;        // [total_cap]
     int *cell_of = nullptr;       // [natoms]
-    int *perm = nullptr;          // sorted slot -> atom
+    int *perm = nullptr;          // cell slot -> atom, as scattered
+    int *sperm = nullptr;         // cell slot -> atom, sorted by atom index within each cell
+    long long *box = nullptr;     // [6 * nclusters] order-preserving encodings of min x,y,z, max x,y,z
+    int4 *chunks = nullptr;       // bounding-box work: (cluster, first atom, end atom, -)
+    int nchunks = 0;
     int *pslot = nullptr;         // atom -> partial index (tile * TILE + li)
     int *atom_cluster = nullptr;  // [natoms]
     double4 *rs = nullptr;        // sorted positions (+ P for the force sweep)
@@ -70,14 +75,29 @@ hipError_t dalloc(T **p, size_t n) {
 // Build kernels
 // ---------------------------------------------------------------------------
 constexpr int kBBoxBlock = 256;
+constexpr int kBBoxChunk = 4096;  // atoms per bounding-box workgroup
 
-__global__ __launch_bounds__(kBBoxBlock) void k_cell_bbox(CellGrid *__restrict__ grid,
-                                                          const double4 *__restrict__ rp, double rc) {
+// Doubles compared as signed 64-bit integers: flip the magnitude bits of
+// negative values (an involution, so the same map decodes).
+__device__ __forceinline__ long long ord_encode(double d) {
+    const long long b = __double_as_longlong(d);
+    return b >= 0 ? b : b ^ 0x7FFFFFFFFFFFFFFFLL;
+}
+__device__ __forceinline__ double ord_decode(long long b) {
+    return __longlong_as_double(b >= 0 ? b : b ^ 0x7FFFFFFFFFFFFFFFLL);
+}
+
+// Partial bounding boxes: one workgroup per chunk of at most kBBoxChunk
+// atoms of one cluster; min/max are exact, so the atomic merge order does not
+// matter.
+__global__ __launch_bounds__(kBBoxBlock) void k_cell_bbox(const int4 *__restrict__ chunks,
+                                                          const double4 *__restrict__ rp,
+                                                          long long *__restrict__ box) {
     __shared__ double sh[6][kBBoxBlock];
-    CellGrid g = grid[blockIdx.x];
+    const int4 ch = chunks[blockIdx.x];
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int i = threadIdx.x; i < g.n; i += kBBoxBlock) {
-        const double4 q = rp[g.off + i];
+    for (int i = ch.y + threadIdx.x; i < ch.z; i += kBBoxBlock) {
+        const double4 q = rp[i];
         lo[0] = fmin(lo[0], q.x);
         lo[1] = fmin(lo[1], q.y);
         lo[2] = fmin(lo[2], q.z);
@@ -99,14 +119,32 @@ __global__ __launch_bounds__(kBBoxBlock) void k_cell_bbox(CellGrid *__restrict__
         }
         __syncthreads();
     }
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x < 3) atomicMin(&box[6 * ch.x + threadIdx.x], ord_encode(sh[threadIdx.x][0]));
+    else if (threadIdx.x < 6) atomicMax(&box[6 * ch.x + threadIdx.x], ord_encode(sh[threadIdx.x][0]));
+}
+
+// Reset the bounding-box accumulators (min slots to +inf, max slots to -inf).
+__global__ __launch_bounds__(64) void k_cell_box_reset(long long *__restrict__ box, int nclusters) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 6 * nclusters) return;
+    box[k] = ord_encode((k % 6) < 3 ? INFINITY : -INFINITY);
+}
+
+// One thread per cluster: cells of edge >= rc over the box (h grows beyond rc
+// only when the box needs more cells than the capacity), then reset the box.
+__global__ __launch_bounds__(64) void k_cell_grid(CellGrid *__restrict__ grid, long long *__restrict__ box,
+                                                  int nclusters, double rc) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nclusters) return;
+    CellGrid g = grid[c];
     const int cap[3] = {g.cx, g.cy, g.cz};
     double o[3], h[3];
     int n[3];
     for (int d = 0; d < 3; ++d) {
-        const double ext = g.n > 0 ? sh[3 + d][0] - sh[d][0] : 0.0;
-        o[d] = g.n > 0 ? sh[d][0] : 0.0;
-        double want = floor(ext / rc) + 1.0;
+        const double lo = ord_decode(box[6 * c + d]), hi = ord_decode(box[6 * c + 3 + d]);
+        const double ext = g.n > 0 ? hi - lo : 0.0;
+        o[d] = g.n > 0 ? lo : 0.0;
+        const double want = floor(ext / rc) + 1.0;
         if (!(want <= (double)cap[d])) {  // too many cells (or non-finite): coarser cells, edge still >= rc
             n[d] = cap[d];
             h[d] = ext / (double)(cap[d] - 1);
@@ -119,6 +157,8 @@ __global__ __launch_bounds__(kBBoxBlock) void k_cell_bbox(CellGrid *__restrict__
             n[d] = (int)want;
             h[d] = rc;
         }
+        box[6 * c + d] = ord_encode(INFINITY);
+        box[6 * c + 3 + d] = ord_encode(-INFINITY);
     }
     g.ox = o[0];
     g.oy = o[1];
@@ -129,7 +169,7 @@ __global__ __launch_bounds__(kBBoxBlock) void k_cell_bbox(CellGrid *__restrict__
     g.nx = n[0];
     g.ny = n[1];
     g.nz = n[2];
-    grid[blockIdx.x] = g;
+    grid[c] = g;
 }
 
 __global__ __launch_bounds__(256) void k_cell_clear(int *__restrict__ count, int total) {
@@ -194,47 +234,65 @@ __global__ __launch_bounds__(256) void k_cell_scatter(const int *__restrict__ ce
     perm[atomicAdd(&cursor[cell_of[i]], 1)] = i;
 }
 
-// One thread per cell: sort its slots by atom index (insertion sort; cells
-// hold tens of atoms), then gather the sorted positions.
-__global__ __launch_bounds__(256) void k_cell_order(const int *__restrict__ start, int *__restrict__ perm,
-                                                    const double4 *__restrict__ rp, double4 *__restrict__ rs,
-                                                    int total) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= total) return;
-    const int a = start[k], b = start[k + 1];
-    for (int p = a + 1; p < b; ++p) {
-        const int v = perm[p];
-        int q = p - 1;
-        while (q >= a && perm[q] > v) {
-            perm[q + 1] = perm[q];
-            --q;
-        }
-        perm[q + 1] = v;
+// One wavefront per cell: the slot of each atom is its rank (the number of
+// atoms of the cell with a smaller index), so sperm lists every cell's atoms
+// in index order whatever order the atomic scatter produced; the sorted
+// positions are gathered at the same time.  Cells larger than the LDS buffer
+// (only after an atom escaped and the cells coarsened) rank from global
+// memory.
+constexpr int kOrderLds = 1024;
+
+__global__ __launch_bounds__(64) void k_cell_order(const int *__restrict__ start, const int *__restrict__ perm,
+                                                   int *__restrict__ sperm, const double4 *__restrict__ rp,
+                                                   double4 *__restrict__ rs) {
+    __shared__ int sh[kOrderLds];
+    const int a = start[blockIdx.x], n = start[blockIdx.x + 1] - a;
+    if (n == 0) return;
+    const bool local = n <= kOrderLds;
+    if (local) {
+        for (int k = threadIdx.x; k < n; k += 64) sh[k] = perm[a + k];
+        __syncthreads();
     }
-    for (int p = a; p < b; ++p) rs[p] = rp[perm[p]];
+    const int *src = local ? sh : perm + a;
+    for (int k = threadIdx.x; k < n; k += 64) {
+        const int v = src[k];
+        int rank = 0;
+        for (int q = 0; q < n; ++q) rank += src[q] < v ? 1 : 0;
+        sperm[a + rank] = v;
+        rs[a + rank] = rp[v];
+    }
 }
 
 // rs[k].w = P of atom perm[k] (after the density sweep has been finished).
-__global__ __launch_bounds__(256) void k_cell_gather_p(const int *__restrict__ perm, const double4 *__restrict__ xp,
+__global__ __launch_bounds__(256) void k_cell_gather_p(const int *__restrict__ sperm, const double4 *__restrict__ xp,
                                                        double4 *__restrict__ rs, int natoms) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= natoms) return;
-    rs[k] = xp[perm[k]];
+    rs[k] = xp[sperm[k]];
 }
 
 // ---------------------------------------------------------------------------
 // Sweeps
 // ---------------------------------------------------------------------------
-template <int W, int PREC, bool GEN, bool FORCE>
-__global__ __launch_bounds__(64 * W) void k_cell_sweep(const CellGrid *__restrict__ grid,
-                                                       const int *__restrict__ cell_cluster,
-                                                       const int *__restrict__ start,
-                                                       const double4 *__restrict__ rs,
-                                                       const int *__restrict__ perm, const int *__restrict__ pslot,
-                                                       double *__restrict__ part, int tile_shift, PotConst pc) {
+// One workgroup of kCellWaves wavefronts per cell.  All wavefronts hold the
+// same 64 atoms of the cell (more in chunks of 64) and split the 9 neighbour
+// rows between them (wavefront w takes rows w, w + W, ...); their sums are
+// combined in LDS in wavefront order.
+constexpr int kCellWaves = 3;
+
+template <int PREC, bool GEN, bool FORCE>
+__global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *__restrict__ grid,
+                                                                const int *__restrict__ cell_cluster,
+                                                                const int *__restrict__ start,
+                                                                const double4 *__restrict__ rs,
+                                                                const int *__restrict__ sperm,
+                                                                const int *__restrict__ pslot,
+                                                                double *__restrict__ part, int tile_shift,
+                                                                PotConst pc) {
+    constexpr int Q = FORCE ? 4 : 1;
+    __shared__ double sh[kCellWaves * Q * 64];
     const int cell = blockIdx.x;
-    const int c = cell_cluster[cell];
-    const CellGrid g = grid[c];
+    const CellGrid g = grid[cell_cluster[cell]];
     const int local = cell - g.base;
     if (local >= g.nx * g.ny * g.nz) return;
     const int s0 = start[cell], cnt = start[cell + 1] - s0;
@@ -243,85 +301,88 @@ __global__ __launch_bounds__(64 * W) void k_cell_sweep(const CellGrid *__restric
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tile = 1 << tile_shift;
     const float Af = (float)pc.A;
-    for (int ci = wave * 64; ci < cnt; ci += W * 64) {
+    for (int ci = 0; ci < cnt; ci += 64) {
         const bool valid = ci + lane < cnt;
         const int k = s0 + ci + lane;
-        double xi = -kFar, yi = -kFar, zi = -kFar, ci_ = 0.0;
+        double xi = -kFar, yi = -kFar, zi = -kFar, c_i = 0.0;
         if (valid) {
             const double4 q = rs[k];
             xi = q.x;
             yi = q.y;
             zi = q.z;
-            ci_ = -q.w;
+            c_i = -q.w;
         }
-        const float cif = (float)ci_;
-        double acc = 0.0, fx = 0.0, fy = 0.0, fz = 0.0, eu = 0.0;
-        for (int dz = -1; dz <= 1; ++dz) {
-            const int jz = iz + dz;
-            if (jz < 0 || jz >= g.nz) continue;
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int jy = iy + dy;
-                if (jy < 0 || jy >= g.ny) continue;
-                const int row = g.base + (jz * g.ny + jy) * g.nx;
-                const int ja = start[row + max(ix - 1, 0)];
-                const int jb = start[row + min(ix + 1, g.nx - 1) + 1];
-                if (dz == 0 && dy == 0) {
-                    for (int j = ja; j < jb; ++j) {
-                        const double4 q = rs[j];
-                        if constexpr (FORCE) {
-                            force_pair<PREC, GEN, true, true>(xi - q.x, yi - q.y, zi - q.z, j == k, ci_, q.w, cif,
-                                                              (float)q.w, fx, fy, fz, eu, pc, Af);
-                        } else {
-                            density_pair<PREC, GEN, true, true>(xi - q.x, yi - q.y, zi - q.z, j == k, acc, pc);
-                        }
-                    }
-                } else {
-                    for (int j = ja; j < jb; ++j) {
-                        const double4 q = rs[j];
-                        if constexpr (FORCE) {
-                            force_pair<PREC, GEN, false, true>(xi - q.x, yi - q.y, zi - q.z, false, ci_, q.w, cif,
-                                                               (float)q.w, fx, fy, fz, eu, pc, Af);
-                        } else {
-                            density_pair<PREC, GEN, false, true>(xi - q.x, yi - q.y, zi - q.z, false, acc, pc);
-                        }
-                    }
+        const float cif = (float)c_i;
+        double acc[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) acc[q] = 0.0;
+        for (int r = wave; r < 9; r += kCellWaves) {
+            const int jz = iz + r / 3 - 1, jy = iy + r % 3 - 1;
+            if (jz < 0 || jz >= g.nz || jy < 0 || jy >= g.ny) continue;
+            const int row = g.base + (jz * g.ny + jy) * g.nx;
+            const int ja = start[row + max(ix - 1, 0)];
+            const int jb = start[row + min(ix + 1, g.nx - 1) + 1];
+            if (r == 4) {  // own row: contains the self pairs
+                for (int j = ja; j < jb; ++j) {
+                    const double4 q = rs[j];
+                    if constexpr (FORCE)
+                        force_pair<PREC, GEN, true, true>(xi - q.x, yi - q.y, zi - q.z, j == k, c_i, q.w, cif,
+                                                          (float)q.w, acc[0], acc[1], acc[2], acc[3], pc, Af);
+                    else
+                        density_pair<PREC, GEN, true, true>(xi - q.x, yi - q.y, zi - q.z, j == k, acc[0], pc);
+                }
+            } else {
+                for (int j = ja; j < jb; ++j) {
+                    const double4 q = rs[j];
+                    if constexpr (FORCE)
+                        force_pair<PREC, GEN, false, true>(xi - q.x, yi - q.y, zi - q.z, false, c_i, q.w, cif,
+                                                           (float)q.w, acc[0], acc[1], acc[2], acc[3], pc, Af);
+                    else
+                        density_pair<PREC, GEN, false, true>(xi - q.x, yi - q.y, zi - q.z, false, acc[0], pc);
                 }
             }
         }
-        if (valid) {
-            const int ps = pslot[perm[k]];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) sh[(wave * Q + q) * 64 + lane] = acc[q];
+        __syncthreads();
+        if (wave == 0 && valid) {
+            double tot[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                tot[q] = sh[q * 64 + lane];
+                for (int w = 1; w < kCellWaves; ++w) tot[q] += sh[(w * Q + q) * 64 + lane];
+            }
+            const int ps = pslot[sperm[k]];
             if constexpr (FORCE) {
                 const int t = ps >> tile_shift, li = ps & (tile - 1);
                 double *out = part + (size_t)t * 4 * tile + li;
-                out[0] = fx;
-                out[tile] = fy;
-                out[2 * tile] = fz;
-                out[3 * tile] = eu;
+                out[0] = tot[0];
+                out[tile] = tot[1];
+                out[2 * tile] = tot[2];
+                out[3 * tile] = tot[3];
             } else {
-                part[ps] = acc;
+                part[ps] = tot[0];
             }
         }
+        __syncthreads();
     }
 }
-
-constexpr int kCellWaves = 2;
 
 template <bool FORCE>
 hipError_t launch_cell_sweep(CellList *cl, double *part, const PotConst &pc, int precision, hipStream_t s) {
     (void)hipGetLastError();
     const dim3 grid(cl->total_cap), block(64 * kCellWaves);
-#define SCMD_CELL_ARGS cl->grid, cl->cell_cluster, cl->start, cl->rs, cl->perm, cl->pslot, part, cl->tile_shift, pc
+#define SCMD_CELL_ARGS cl->grid, cl->cell_cluster, cl->start, cl->rs, cl->sperm, cl->pslot, part, cl->tile_shift, pc
     if (precision == SCMD_FP64) {
         if (pc.generic)
-            hipLaunchKernelGGL((k_cell_sweep<kCellWaves, SCMD_FP64, true, FORCE>), grid, block, 0, s, SCMD_CELL_ARGS);
+            hipLaunchKernelGGL((k_cell_sweep<SCMD_FP64, true, FORCE>), grid, block, 0, s, SCMD_CELL_ARGS);
         else
-            hipLaunchKernelGGL((k_cell_sweep<kCellWaves, SCMD_FP64, false, FORCE>), grid, block, 0, s, SCMD_CELL_ARGS);
+            hipLaunchKernelGGL((k_cell_sweep<SCMD_FP64, false, FORCE>), grid, block, 0, s, SCMD_CELL_ARGS);
     } else {
         if (pc.generic)
-            hipLaunchKernelGGL((k_cell_sweep<kCellWaves, SCMD_MIXED, true, FORCE>), grid, block, 0, s, SCMD_CELL_ARGS);
+            hipLaunchKernelGGL((k_cell_sweep<SCMD_MIXED, true, FORCE>), grid, block, 0, s, SCMD_CELL_ARGS);
         else
-            hipLaunchKernelGGL((k_cell_sweep<kCellWaves, SCMD_MIXED, false, FORCE>), grid, block, 0, s,
-                               SCMD_CELL_ARGS);
+            hipLaunchKernelGGL((k_cell_sweep<SCMD_MIXED, false, FORCE>), grid, block, 0, s, SCMD_CELL_ARGS);
     }
 #undef SCMD_CELL_ARGS
     return hipGetLastError();
@@ -341,8 +402,8 @@ CellList *cell_list_create() {
 
 void cell_list_destroy(CellList *cl) {
     if (!cl) return;
-    void *ptrs[] = {cl->grid, cl->cell_cluster, cl->count, cl->start, cl->cursor, cl->cell_of,
-                    cl->perm, cl->pslot, cl->atom_cluster, cl->rs};
+    void *ptrs[] = {cl->grid,  cl->cell_cluster, cl->count, cl->start,        cl->cursor, cl->cell_of, cl->perm,
+                    cl->sperm, cl->box,          cl->chunks, cl->pslot, cl->atom_cluster, cl->rs};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete cl;
@@ -382,7 +443,7 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
         int cap[3];
         for (int d = 0; d < 3; ++d) {
             const int n0 = (int)std::floor((hi[d] - lo[d]) / rc) + 1;
-            cap[d] = std::min(2 * n0 + 4, 1024);
+            cap[d] = std::min(n0 + 4, 1024);
         }
         g.cx = cap[0];
         g.cy = cap[1];
@@ -396,6 +457,11 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
         grids[c] = g;
     }
     cl->total_cap = base;
+    std::vector<int4> chunks;
+    for (int c = 0; c < nclusters; ++c)
+        for (int a = (int)offsets[c]; a < (int)offsets[c + 1]; a += kBBoxChunk)
+            chunks.push_back(make_int4(c, a, std::min<int>(a + kBBoxChunk, (int)offsets[c + 1]), 0));
+    cl->nchunks = (int)chunks.size();
     std::vector<int> pslot(natoms), ac(natoms);
     for (int t = 0; t < ntiles; ++t)
         for (int li = 0; li < tiles[t].ni; ++li) {
@@ -409,6 +475,15 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
     if ((e = dalloc(&cl->cursor, base)) != hipSuccess) return e;
     if ((e = dalloc(&cl->cell_of, natoms)) != hipSuccess) return e;
     if ((e = dalloc(&cl->perm, natoms)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->sperm, natoms)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->box, 6 * nclusters)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->chunks, chunks.size())) != hipSuccess) return e;
+    if (!chunks.empty() &&
+        (e = hipMemcpy(cl->chunks, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_cell_box_reset, dim3((6 * nclusters + 63) / 64), dim3(64), 0, 0, cl->box, nclusters);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
     if ((e = dalloc(&cl->pslot, natoms)) != hipSuccess) return e;
     if ((e = dalloc(&cl->atom_cluster, natoms)) != hipSuccess) return e;
     if ((e = dalloc(&cl->rs, natoms)) != hipSuccess) return e;
@@ -429,7 +504,10 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
 hipError_t cell_list_build(CellList *cl, const double4 *rp, hipStream_t s) {
     (void)hipGetLastError();
     const int na = cl->natoms, tc = cl->total_cap;
-    hipLaunchKernelGGL(k_cell_bbox, dim3(cl->nclusters), dim3(kBBoxBlock), 0, s, cl->grid, rp, cl->rc);
+    if (cl->nchunks > 0)
+        hipLaunchKernelGGL(k_cell_bbox, dim3(cl->nchunks), dim3(kBBoxBlock), 0, s, cl->chunks, rp, cl->box);
+    hipLaunchKernelGGL(k_cell_grid, dim3((cl->nclusters + 63) / 64), dim3(64), 0, s, cl->grid, cl->box, cl->nclusters,
+                       cl->rc);
     hipLaunchKernelGGL(k_cell_clear, dim3((tc + 255) / 256), dim3(256), 0, s, cl->count, tc);
     if (na > 0)
         hipLaunchKernelGGL(k_cell_count, dim3((na + 255) / 256), dim3(256), 0, s, cl->grid, cl->atom_cluster, rp,
@@ -438,7 +516,7 @@ hipError_t cell_list_build(CellList *cl, const double4 *rp, hipStream_t s) {
     if (na > 0)
         hipLaunchKernelGGL(k_cell_scatter, dim3((na + 255) / 256), dim3(256), 0, s, cl->cell_of, cl->cursor, cl->perm,
                            na);
-    hipLaunchKernelGGL(k_cell_order, dim3((tc + 255) / 256), dim3(256), 0, s, cl->start, cl->perm, rp, cl->rs, tc);
+    hipLaunchKernelGGL(k_cell_order, dim3(tc), dim3(64), 0, s, cl->start, cl->perm, cl->sperm, rp, cl->rs);
     return hipGetLastError();
 }
 
@@ -453,7 +531,7 @@ hipError_t cell_list_force(CellList *cl, const SweepBuffers &B, const StepArgs &
                            int tile, const PotConst &pc, int precision, hipStream_t s) {
     (void)hipGetLastError();
     if (cl->natoms > 0)
-        hipLaunchKernelGGL(k_cell_gather_p, dim3((cl->natoms + 255) / 256), dim3(256), 0, s, cl->perm, B.xp, cl->rs,
+        hipLaunchKernelGGL(k_cell_gather_p, dim3((cl->natoms + 255) / 256), dim3(256), 0, s, cl->sperm, B.xp, cl->rs,
                            cl->natoms);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -163,6 +163,7 @@ hipError_t launch_sym_force(const SymLaunch &L, const SweepBuffers &B, const Ste
 // Per-cluster energies, temperature and thermostat factor from the tile sums.
 hipError_t launch_finalize(const StepArgs &a, const double *tile_sums, int nclusters, hipStream_t s);
 
+
 hipError_t launch_drift(const int32_t *atom_cluster, const ClusterState *st, double4 *rp, double4 *v,
                         const double4 *f, int natoms, double dt, double h, hipStream_t s);
 hipError_t launch_aos_from4(const double4 *src, double *dst, int natoms, hipStream_t s);

@@ -235,16 +235,11 @@ void harvest_events(scmd_ctx *c) {
 void default_shape(const scmd_ctx *c, int *ipt, int *wi, int *wj, int *target) {
     int64_t nmax = 0;
     for (int k = 0; k < c->nclusters; ++k) nmax = std::max<int64_t>(nmax, c->offsets[k + 1] - c->offsets[k]);
-    if (c->nclusters > 1) {  // batches: (2,1,4), fine work splitting
-        *ipt = 2;
-        *wi = 1;
-        *wj = 4;
-        *target = 8192;
-    } else if (nmax <= 4096) {  // small single clusters: latency-bound
+    if (nmax <= 4096) {  // small clusters: latency-bound, many short partner loops
         *ipt = 1;
         *wi = 1;
         *wj = 8;
-        *target = 2048;
+        *target = 8192;
     } else {
         *ipt = 2;
         *wi = 1;
@@ -356,11 +351,19 @@ int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
     {
         int64_t nmax = 0;
         for (int k = 0; k < c->nclusters; ++k) nmax = std::max<int64_t>(nmax, c->offsets[k + 1] - c->offsets[k]);
+        // Library choice (from the autotuner on MI355X): symmetric sweeps for
+        // batches and for clusters above 4096 atoms; IPT 4 and fine splitting
+        // for batches and very large clusters, IPT 2 in between.
         const bool allowed = c->neighbour == SCMD_ALLPAIRS && !c->pc.generic;
-        c->sym = allowed && (c->tuning.pairs == 2 || (c->tuning.pairs == 0 && nmax >= 8192));
+        const bool batch = c->nclusters > 1;
+        c->sym = allowed && (c->tuning.pairs == 2 || (c->tuning.pairs == 0 && (batch || nmax > 4096)));
         if (c->sym) {
-            c->sym_ipt = (c->tuning.ipt == 2 || c->tuning.ipt == 4) ? c->tuning.ipt : 4;
-            return build_sym_plan(c, c->tuning.target_items > 0 ? c->tuning.target_items : 4096);
+            int ipt = (batch || nmax > 32768) ? 4 : 2;
+            int target = batch ? 8192 : (nmax > 32768 ? 4096 : 2048);
+            if (c->tuning.ipt == 2 || c->tuning.ipt == 4) ipt = c->tuning.ipt;
+            if (c->tuning.target_items > 0) target = c->tuning.target_items;
+            c->sym_ipt = ipt;
+            return build_sym_plan(c, target);
         }
     }
     int target = 2048;
@@ -540,7 +543,9 @@ hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int adv
 
 // rho, F, energies at the current positions; advance = 1 also kicks and
 // runs the thermostat (second half of a step).
-hipError_t enqueue_forces(scmd_ctx *c, hipStream_t s, bool capturing, int advance) {
+// Sweeps and tile finishes of one force evaluation (everything but the
+// per-cluster finalize).
+hipError_t enqueue_sweeps(scmd_ctx *c, hipStream_t s, bool capturing, int advance) {
     hipError_t e;
     const SweepBuffers B = buffers(c);
     const StepArgs A = step_args(c, advance);
@@ -550,8 +555,7 @@ hipError_t enqueue_forces(scmd_ctx *c, hipStream_t s, bool capturing, int advanc
         if ((e = sweep(c, false, s, capturing, advance)) != hipSuccess) return e;
         if ((e = launch_sym_density(L, B, c->pc, c->precision, 1, s)) != hipSuccess) return e;
         if ((e = sweep(c, true, s, capturing, advance)) != hipSuccess) return e;
-        if ((e = launch_sym_force(L, B, A, c->pc, c->precision, 1, s)) != hipSuccess) return e;
-        return launch_finalize(A, c->d_tile_sums.p, c->nclusters, s);
+        return launch_sym_force(L, B, A, c->pc, c->precision, 1, s);
     }
     if (c->neighbour == SCMD_CELLLIST) {
         if ((e = cell_list_build(c->cells, c->rp.p, s)) != hipSuccess) return e;
@@ -562,14 +566,30 @@ hipError_t enqueue_forces(scmd_ctx *c, hipStream_t s, bool capturing, int advanc
     if ((e = sweep(c, true, s, capturing, advance)) != hipSuccess) return e;
     if (c->has_split && (e = launch_force_reduce(c->d_tiles.p, c->ntiles, c->tile, B, A, c->pc, 2, s)) != hipSuccess)
         return e;
-    return launch_finalize(A, c->d_tile_sums.p, c->nclusters, s);
+    return hipSuccess;
 }
 
-hipError_t enqueue_step(scmd_ctx *c, hipStream_t s, bool capturing) {
-    hipError_t e = launch_drift(c->atom_cluster.p, c->d_state.p, c->rp.p, c->v.p, c->f.p, c->natoms, c->dt,
-                                half_kick(c), s);
+// rho, F, energies at the current positions; advance = 1 also kicks and
+// runs the thermostat (second half of a step).
+hipError_t enqueue_forces(scmd_ctx *c, hipStream_t s, bool capturing, int advance) {
+    hipError_t e = enqueue_sweeps(c, s, capturing, advance);
     if (e != hipSuccess) return e;
-    return enqueue_forces(c, s, capturing, 1);
+    return launch_finalize(step_args(c, advance), c->d_tile_sums.p, c->nclusters, s);
+}
+
+// A run of nsteps velocity-Verlet steps; the last step of a captured run
+// carries the sampled profiling events.
+hipError_t enqueue_run(scmd_ctx *c, hipStream_t s, bool capturing, int64_t nsteps) {
+    hipError_t e;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        e = launch_drift(c->atom_cluster.p, c->d_state.p, c->rp.p, c->v.p, c->f.p, c->natoms, c->dt, half_kick(c), s);
+        if (e != hipSuccess) return e;
+        if (capturing) c->capture_sample = (k == nsteps - 1);
+        e = enqueue_forces(c, s, capturing, 1);
+        if (e != hipSuccess) return e;
+    }
+    c->capture_sample = false;
+    return hipSuccess;
 }
 
 int ensure_graph(scmd_ctx *c) {
@@ -577,12 +597,7 @@ int ensure_graph(scmd_ctx *c) {
     drop_graph(c);
     hipGraph_t g = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    for (int k = 0; k < kGraphSteps && e == hipSuccess; ++k) {
-        c->capture_sample = (k == kGraphSteps - 1);
-        e = enqueue_step(c, c->cap_stream, true);
-    }
-    c->capture_sample = false;
+    hipError_t e = enqueue_run(c, c->cap_stream, true, kGraphSteps);
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -637,7 +652,7 @@ int enqueue_steps(scmd_ctx *c, int64_t nsteps) {
         for (int64_t r = 0; r < full; ++r) HIP_TRY(c, hipGraphLaunch(c->graph, c->stream));
         c->graph_unread = c->profiling != 0;
     }
-    for (int64_t r = 0; r < rem; ++r) HIP_TRY(c, enqueue_step(c, c->stream, false));
+    if (rem > 0) HIP_TRY(c, enqueue_run(c, c->stream, false, rem));
     c->step += nsteps;
     return SCMD_OK;
 }

@@ -264,8 +264,9 @@ __device__ __forceinline__ void force_atom(int i, double fx, double fy, double f
 
 // Per-cluster finish, run by one whole workgroup per cluster: fixed-order
 // sums of the tile sums, then temperature and the Berendsen factor.
+// Returns the cluster's current thermostat factor to thread 0.
 template <int BLOCK>
-__device__ void cluster_finalize(int c, const FinalizeArgs &o, double *sh) {
+__device__ double cluster_finalize(int c, const FinalizeArgs &o, double *sh) {
     const ClusterDesc d = o.cd[c];
     double emb = 0.0, epair = 0.0, v2 = 0.0;
     for (int t = threadIdx.x; t < d.ntiles; t += BLOCK) {
@@ -277,7 +278,7 @@ __device__ void cluster_finalize(int c, const FinalizeArgs &o, double *sh) {
     emb = block_sum<BLOCK>(emb, sh);
     epair = block_sum<BLOCK>(epair, sh);
     v2 = block_sum<BLOCK>(v2, sh);
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x != 0) return 1.0;
     ClusterState s = o.st[c];
     const double ke = 0.5 * o.mass_u * v2 * kEvPerUA2Fs2;
     const double T = d.ndof > 0 ? 2.0 * ke / ((double)d.ndof * kBoltzmannEv) : 0.0;
@@ -308,6 +309,7 @@ __device__ void cluster_finalize(int c, const FinalizeArgs &o, double *sh) {
         atomicOr(o.flag, 1);
     }
     o.st[c] = s;
+    return s.lambda;
 }
 
 }  // namespace dev

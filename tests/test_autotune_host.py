@@ -1,0 +1,36 @@
+"""Autotuner host logic (no GPU): cache keys and lookups."""
+import json
+
+import numpy as np
+
+from paper_1210_3559_amd import autotune
+
+
+def test_bucket_groups_by_size_and_count():
+    a = autotune.bucket(np.array([0, 2243]), "fp64")
+    b = autotune.bucket(np.array([0, 3000]), "fp64")
+    c = autotune.bucket(np.array([0, 5000]), "fp64")
+    assert a == b != c
+    assert autotune.bucket(np.array([0, 2243]), "mixed") != a
+    batch = autotune.bucket(np.concatenate([[0], np.cumsum(np.full(256, 100))]), "fp64")
+    assert batch.endswith("nc2^8")
+
+
+def test_lookup_reads_cache(tmp_path):
+    path = tmp_path / "cache.json"
+    key = autotune.bucket(np.array([0, 2243]), "fp64")
+    path.write_text(json.dumps({key: {"tuning": {"ipt": 1, "waves_i": 1, "waves_j": 8, "target_items": 2048,
+                                                 "pairs": 1}, "ms_per_step": 0.03}}))
+    t = autotune.lookup(np.array([0, 2100]), "fp64", str(path))
+    assert t == {"ipt": 1, "waves_i": 1, "waves_j": 8, "target_items": 2048, "pairs": 1}
+    assert autotune.lookup(np.array([0, 20000]), "fp64", str(path)) is None
+    assert autotune.lookup(np.array([0, 20]), "fp64", str(tmp_path / "missing.json")) is None
+
+
+def test_candidate_shapes_are_supported_by_the_header():
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "scmd.h")).read()
+    listed = set(re.findall(r"\((\d),(\d),(\d+)\)", hdr))
+    for s in autotune.SHAPES:
+        assert tuple(str(x) for x in s) in listed, s
