@@ -41,6 +41,25 @@ FLOP_DENSITY_PER_PAIR = 13.0  # algorithmic FLOP per unordered pair, density swe
 FLOP_FORCE_PER_PAIR = 31.0  # algorithmic FLOP per unordered pair, force sweep
 
 
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (profiles/traffic.json), or None when the kernel sources changed
+    since the counters were taken or the workload was not measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec.get("sources", []):
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec.get("sha256"):
+        return None
+    return rec.get("dominant_bytes_per_launch", {}).get(workload)
+
+
 def _pairs(sizes) -> int:
     s = np.asarray(sizes, dtype=np.int64)
     return int(np.sum(s * (s - 1) // 2))
@@ -152,6 +171,9 @@ def main(argv=None):
     ap.add_argument("--no-forms", action="store_true", help="skip the extra forms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the run, copy this many MiB device-to-device once (a plain copy kernel of known "
+                         "size, to scale hardware byte counters when profiling)")
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -164,8 +186,21 @@ def main(argv=None):
     print(f"[bench] {w.name}: {w.n_atoms} atoms, {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
           flush=True)
     main_res = time_gpu(w, args.steps, args.warmup)
+    if main_res.get("roofline") is not None:
+        main_res["roofline"]["traffic"] = measured_traffic(args.workload)
     print(f"[bench] {main_res['atom_steps_per_s']:.4e} atom-steps/s, {main_res['ms_per_step']:.4f} ms/step",
           file=sys.stderr, flush=True)
+
+    if args.copy_mib > 0:
+        import torch
+        n = args.copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copied {args.copy_mib} MiB ({n * 8} bytes) device to device", file=sys.stderr, flush=True)
+        del src, dst
 
     forms = {}
     if not args.no_forms:
