@@ -24,6 +24,8 @@ from . import scmd
 SHAPES = [(1, 4, 1), (2, 4, 1), (1, 2, 2), (2, 2, 2), (1, 1, 4), (2, 1, 4), (1, 2, 4), (2, 2, 4), (1, 4, 4),
           (1, 1, 8), (2, 1, 8), (1, 2, 8), (1, 1, 16), (4, 1, 2), (4, 1, 4), (4, 2, 2)]
 TARGETS = [1, 512, 2048, 8192]
+ROW_WAVES = [4, 8, 16]
+ROW_TARGETS = [256, 512, 1024]  # workgroups per row sweep
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 ARCH = "gfx950"
 
@@ -41,16 +43,18 @@ def _time(sim: "scmd.Simulation", steps: int) -> float:
 
 
 def tune(w, precision: str | None = None, budget_s: float = 0.25, shapes=SHAPES, targets=TARGETS, verbose=True,
-         symmetric: bool = True):
+         symmetric: bool = True, row: bool = True):
     """Time every shape/target on workload w; returns (best tuning dict, table)."""
     precision = precision or w.precision
     pairs = float(np.sum(w.sizes().astype(np.float64) ** 2))
     table = []
-    candidates = [dict(ipt=ipt, waves_i=wi, waves_j=wj, pairs=1) for ipt, wi, wj in shapes]
+    candidates = [(dict(ipt=ipt, waves_i=wi, waves_j=wj, pairs=1), targets) for ipt, wi, wj in shapes]
     if symmetric:
-        candidates += [dict(ipt=ipt, pairs=2) for ipt in (2, 4)]
-    for cand in candidates:
-        for tgt in targets:
+        candidates += [(dict(ipt=ipt, pairs=2), targets) for ipt in (2, 4)]
+    if row:
+        candidates += [(dict(waves_j=wv, pairs=3), ROW_TARGETS) for wv in ROW_WAVES]
+    for cand, tgts in candidates:
+        for tgt in tgts:
             tun = dict(cand, target_items=tgt)
             with scmd.Simulation.from_workload(w, precision=precision, tuning=tun) as sim:
                 sim.step(32)

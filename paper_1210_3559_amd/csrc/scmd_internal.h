@@ -160,6 +160,21 @@ hipError_t launch_sym_density(const SymLaunch &L, const SweepBuffers &B, const P
 hipError_t launch_sym_force(const SymLaunch &L, const SweepBuffers &B, const StepArgs &a, const PotConst &pc,
                             int precision, int stage, hipStream_t s);
 
+// Row sweeps for small clusters: one workgroup of 64 * waves threads per
+// tile of at most 64 atoms against every partner of the tile's cluster;
+// each sweep finishes its tiles in the same launch (no partial slots).
+struct RowLaunch {
+    const ITile *tiles;
+    const int32_t *order;  // launch order of the tiles
+    const ClusterDesc *cd;
+    int ntiles;
+    int waves;             // 4, 8 or 16
+};
+hipError_t launch_row_density(const RowLaunch &L, const SweepBuffers &B, const PotConst &pc, int precision,
+                              hipStream_t s);
+hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, const PotConst &pc,
+                            int precision, hipStream_t s);
+
 // Per-cluster energies, temperature and thermostat factor from the tile sums.
 hipError_t launch_finalize(const StepArgs &a, const double *tile_sums, int nclusters, hipStream_t s);
 

@@ -98,6 +98,8 @@ struct scmd_ctx {
     bool has_split = false;  // some tile's partner range spans several items
 
     // symmetric all-pairs plan
+    bool row = false;       // row sweeps (small clusters, no partial slots)
+    int row_waves = 16;
     bool sym = false;
     int sym_ipt = 4, sym_nitems = 0, sym_ntiles = 0;
     DevBuf<SymItem> d_sitems;
@@ -346,8 +348,72 @@ int build_sym_plan(scmd_ctx *c, int target) {
     return SCMD_OK;
 }
 
+// Row plan: tiles of ni <= 64 atoms, one workgroup each, sized so that the
+// sweep has about `target` workgroups of about equal work (ni n_c).
+int build_row_plan(scmd_ctx *c, int target, std::vector<ITile> *tiles_out) {
+    double total = 0.0;
+    for (int k = 0; k < c->nclusters; ++k) {
+        const double n = (double)(c->offsets[k + 1] - c->offsets[k]);
+        total += n * n;
+    }
+    const double wstar = std::max(1.0, total / std::max(1, target));
+    std::vector<ITile> tiles;
+    int tmax = 1;
+    for (int k = 0; k < c->nclusters; ++k) {
+        ClusterDesc &d = c->cdesc[k];
+        const int off = (int)c->offsets[k];
+        const int n = (int)(c->offsets[k + 1] - c->offsets[k]);
+        const int ni = n > 0 ? (int)std::min<double>(64.0, std::max(1.0, std::ceil(wstar / n))) : 1;
+        d.off = off;
+        d.n = n;
+        d.tile0 = (int)tiles.size();
+        d.ntiles = (n + ni - 1) / ni;
+        d.ndof = ndof_of(n);
+        for (int t = 0; t < d.ntiles; ++t) {
+            ITile T{};
+            T.c = k;
+            T.i0 = off + t * ni;
+            T.ni = std::min(ni, n - t * ni);
+            T.first = 0;
+            T.nsplit = 1;
+            tiles.push_back(T);
+        }
+        tmax = std::max(tmax, ni);
+    }
+    std::vector<int32_t> order(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        const int64_t wx = (int64_t)tiles[x].ni * c->cdesc[tiles[x].c].n;
+        const int64_t wy = (int64_t)tiles[y].ni * c->cdesc[tiles[y].c].n;
+        return wx > wy;
+    });
+    c->tile = tmax;
+    c->nitems = 0;
+    c->ntiles = (int)tiles.size();
+    c->has_split = false;
+    HIP_TRY(c, c->d_items.ensure(1));
+    HIP_TRY(c, c->d_order.ensure(std::max<size_t>(order.size(), 1)));
+    HIP_TRY(c, c->d_tiles.ensure(std::max<size_t>(tiles.size(), 1)));
+    HIP_TRY(c, c->d_part.ensure(1));
+    HIP_TRY(c, c->d_tile_sums.ensure(std::max<size_t>((size_t)tiles.size() * kTileSums, 1)));
+    HIP_TRY(c, c->d_cdesc.ensure(std::max<size_t>(c->cdesc.size(), 1)));
+    HIP_TRY(c, c->xp.ensure(std::max<size_t>(c->natoms, 1)));
+    HIP_TRY(c, hipMemset(c->d_tile_sums.p, 0, c->d_tile_sums.n * sizeof(double)));
+    if (!tiles.empty()) {
+        HIP_TRY(c, hipMemcpy(c->d_order.p, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(c->d_tiles.p, tiles.data(), tiles.size() * sizeof(ITile), hipMemcpyHostToDevice));
+    }
+    if (!c->cdesc.empty())
+        HIP_TRY(c, hipMemcpy(c->d_cdesc.p, c->cdesc.data(), c->cdesc.size() * sizeof(ClusterDesc),
+                             hipMemcpyHostToDevice));
+    if (tiles_out) *tiles_out = tiles;
+    c->plan_ok = true;
+    return SCMD_OK;
+}
+
 int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
     c->plan_ok = false;
+    c->row = false;
     {
         int64_t nmax = 0;
         for (int k = 0; k < c->nclusters; ++k) nmax = std::max<int64_t>(nmax, c->offsets[k + 1] - c->offsets[k]);
@@ -356,6 +422,16 @@ int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
         // for batches and very large clusters, IPT 2 in between.
         const bool allowed = c->neighbour == SCMD_ALLPAIRS && !c->pc.generic;
         const bool batch = c->nclusters > 1;
+        // row sweeps: single clusters up to 4096 atoms, unless a one-sided
+        // launch shape was given
+        const bool shape_given = c->tuning.ipt > 0 || c->tuning.waves_i > 0 || c->tuning.waves_j > 0;
+        const bool row_default = !batch && nmax <= 4096 && !shape_given;
+        if (c->neighbour == SCMD_ALLPAIRS && (c->tuning.pairs == 3 || (c->tuning.pairs == 0 && row_default))) {
+            c->sym = false;
+            c->row = true;
+            c->row_waves = c->tuning.waves_j > 0 ? c->tuning.waves_j : 16;
+            return build_row_plan(c, c->tuning.target_items > 0 ? c->tuning.target_items : 256, tiles_out);
+        }
         c->sym = allowed && (c->tuning.pairs == 2 || (c->tuning.pairs == 0 && (batch || nmax > 4096)));
         if (c->sym) {
             int ipt = (batch || nmax > 32768) ? 4 : 2;
@@ -525,6 +601,9 @@ hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int adv
                           c->d_ipart.p, c->d_jpart.p};
         e = force ? launch_sym_force(L, B, A, c->pc, c->precision, 0, s)
                   : launch_sym_density(L, B, c->pc, c->precision, 0, s);
+    } else if (c->row) {
+        const RowLaunch R{c->d_tiles.p, c->d_order.p, c->d_cdesc.p, c->ntiles, c->row_waves};
+        e = force ? launch_row_force(R, B, A, c->pc, c->precision, s) : launch_row_density(R, B, c->pc, c->precision, s);
     } else if (c->neighbour == SCMD_CELLLIST) {
         e = force ? cell_list_force(c->cells, B, A, c->d_tiles.p, c->ntiles, c->tile, c->pc, c->precision, s)
                   : cell_list_density(c->cells, B, c->d_tiles.p, c->ntiles, c->tile, c->pc, c->precision, s);
@@ -991,12 +1070,15 @@ int scmd_set_tuning(scmd_ctx *ctx, const scmd_tuning *t) {
         if (t->pairs == 2) {
             if (t->ipt != 0 && t->ipt != 2 && t->ipt != 4)
                 return fail(ctx, SCMD_EINVAL, "symmetric sweeps take ipt 2 or 4");
+        } else if (t->pairs == 3) {
+            if (t->waves_j != 0 && t->waves_j != 4 && t->waves_j != 8 && t->waves_j != 16)
+                return fail(ctx, SCMD_EINVAL, "row sweeps take waves_j 4, 8 or 16");
         } else if (t->ipt != 0 || t->waves_i != 0 || t->waves_j != 0) {
             if (!shape_supported(t->ipt, t->waves_i, t->waves_j))
                 return fail(ctx, SCMD_EINVAL, "unsupported (ipt, waves_i, waves_j) launch shape");
         }
         if (t->target_items < 0) return fail(ctx, SCMD_EINVAL, "target_items must be >= 0");
-        if (t->pairs < 0 || t->pairs > 2) return fail(ctx, SCMD_EINVAL, "pairs must be 0, 1 or 2");
+        if (t->pairs < 0 || t->pairs > 3) return fail(ctx, SCMD_EINVAL, "pairs must be 0, 1, 2 or 3");
         z = *t;
     }
     (void)hipSetDevice(ctx->device);

@@ -106,11 +106,13 @@ def test_compute_parity_mixed(n):
     check_single(pos, precision="mixed")
 
 
+@pytest.mark.parametrize("pairs", [0, 1])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("nm", [(12, 6), (10, 7), (8, 5)])
-def test_generic_exponents(precision, nm):
+def test_generic_exponents(precision, nm, pairs):
     n, m = nm
-    check_single(_cluster(300, seed=3), precision=precision, params=dict(n=n, m=m))
+    tuning = dict(pairs=1, ipt=1, waves_i=4, waves_j=1) if pairs == 1 else None
+    check_single(_cluster(300, seed=3), precision=precision, params=dict(n=n, m=m), tuning=tuning)
 
 
 def test_batch_parity_with_empty_and_tiny_clusters():
@@ -459,3 +461,79 @@ def test_symmetric_trajectory_parity_and_determinism():
     assert np.abs(outs[0][0] - r_ref).max() < 1e-10
     assert np.abs(outs[0][1] - v_ref).max() < 1e-11
     assert outs[0][2][0] == pytest.approx(log[39, 0], rel=1e-10)
+
+
+# --------------------------------------------------------------------------
+# Row sweeps: one workgroup per run of at most 64 atoms against all of its
+# partners, finished in the same launch
+# --------------------------------------------------------------------------
+_ROW_CACHE = {}
+
+
+def _row_case(n):
+    if n not in _ROW_CACHE:
+        pos = inputs.c2_cooling().pos if n == 2243 else _cluster(n, seed=500 + n)
+        _ROW_CACHE[n] = (pos, oracle.forces(pos, nthreads=NT))
+    return _ROW_CACHE[n]
+
+
+@pytest.mark.parametrize("target", [0, 1, 97, 100000])
+@pytest.mark.parametrize("waves", [4, 8, 16])
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 65, 147, 257, 1000, 2243, 4097])
+def test_row_compute_parity(n, waves, target):
+    # target 1: 64-atom runs (one stream per thread group of 64); 100000: one
+    # atom per workgroup (64 * waves streams); 97: ragged run lengths
+    pos, (f_ref, rho_ref, site) = _row_case(n)
+    tuning = dict(pairs=3, waves_j=waves, target_items=target)
+    print(f"[parity] row n={n} tuning={tuning}", flush=True)
+    f, rho, ens = run_compute(np.array([0, n]), pos, "fp64", tuning)
+    assert_forces_close(f, f_ref, 1e-10)
+    np.testing.assert_allclose(rho, rho_ref, rtol=1e-10, atol=0)
+    assert abs(ens[0][0] - site.sum()) <= 1e-10 * max(abs(site.sum()), 1e-300)
+
+
+@pytest.mark.parametrize("n", [147, 300, 2243])
+def test_row_compute_parity_mixed(n):
+    pos = inputs.c1_icosahedron().pos if n == 147 else _cluster(n, seed=9)
+    check_single(pos, precision="mixed", tuning=dict(pairs=3, waves_j=8))
+
+
+def test_row_batch_parity():
+    sizes = [147, 0, 1, 2, 333, 64, 1000, 5, 129]
+    parts = [_cluster(s, seed=40 + k, amp=0.1) for k, s in enumerate(sizes)]
+    pos = np.concatenate(parts)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    print(f"[parity] row batch sizes={sizes}", flush=True)
+    with scmd.Simulation(offsets, pos, None, tuning=dict(pairs=3, waves_j=8, target_items=50)) as sim:
+        sim.compute()
+        f, rho = sim.forces(), sim.density()
+        ens = [sim.energy(k) for k in range(len(sizes))]
+    for k, p in enumerate(parts):
+        a, b = offsets[k], offsets[k + 1]
+        if b == a:
+            assert ens[k] == (0.0, 0.0, 0.0)
+            continue
+        f_ref, rho_ref, site = oracle.forces(p, nthreads=NT)
+        assert_forces_close(f[a:b], f_ref, 1e-10)
+        np.testing.assert_allclose(rho[a:b], rho_ref, rtol=1e-10)
+        assert ens[k][0] == pytest.approx(site.sum(), rel=1e-10)
+
+
+@pytest.mark.parametrize("waves", [4, 8, 16])
+def test_row_trajectory_parity_and_determinism(waves):
+    w = inputs.c2_cooling()
+    th = w.thermostat[0]
+    r_ref, v_ref, _, log = oracle.vv_run(w.pos, w.vel, 40, dt=w.dt, thermostat=th, nthreads=NT)
+    outs = []
+    print(f"[parity] row trajectory waves={waves}", flush=True)
+    for _ in range(2):
+        with scmd.Simulation.from_workload(w, tuning=dict(pairs=3, waves_j=waves)) as sim:
+            sim.step(40)
+            outs.append((sim.positions(), sim.velocities(), sim.energy(), sim.temperature()))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    assert np.abs(outs[0][0] - r_ref).max() < 1e-10
+    assert np.abs(outs[0][1] - v_ref).max() < 1e-11
+    assert outs[0][2][0] == pytest.approx(log[39, 0], rel=1e-10)
+    assert outs[0][2][1] == pytest.approx(log[39, 1], rel=1e-10)
+    assert outs[0][3][0] == pytest.approx(log[39, 2], rel=1e-10)
