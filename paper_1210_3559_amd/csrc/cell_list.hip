@@ -342,6 +342,7 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
                 }
             }
         }
+        if constexpr (FORCE) unscale_force<PREC, GEN>(acc[0], acc[1], acc[2], acc[3]);
 #pragma unroll
         for (int q = 0; q < Q; ++q) sh[(wave * Q + q) * 64 + lane] = acc[q];
         __syncthreads();

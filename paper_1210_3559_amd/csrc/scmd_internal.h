@@ -33,6 +33,8 @@ struct PotConst {
     double rc2;       // rc^2 (0: all pairs)
     double inv_rc_m;  // rc^-m  (shift of u^m)
     double inv_rc_n;  // rc^-n  (shift of u^n)
+    double A8;        // A / 8          (force term evaluated with 2u, (n, m) = (9, 6))
+    double inv_rc_n512;  // 512 rc^-n   (shift of (2u)^9)
     int n, m;
     int cut;          // 1 when rc > 0
     int generic;      // 1 unless (n, m) == (9, 6)
@@ -175,8 +177,14 @@ hipError_t launch_row_density(const RowLaunch &L, const SweepBuffers &B, const P
 hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, const PotConst &pc,
                             int precision, hipStream_t s);
 
-// Per-cluster energies, temperature and thermostat factor from the tile sums.
-hipError_t launch_finalize(const StepArgs &a, const double *tile_sums, int nclusters, hipStream_t s);
+// Per-cluster energies, temperature and thermostat factor from the tile sums;
+// step_add = steps completed since the cluster step counter was last stored
+// (1 after every step; 0 for an evaluation without motion).
+hipError_t launch_finalize(const StepArgs &a, const double *tile_sums, int nclusters, int step_add, hipStream_t s);
+// Single cluster: the finish of the run's step `local` (>= 1, counted from the
+// start of the run, counter not stored) fused with the drift of step local+1.
+hipError_t launch_drift_fin(const StepArgs &a, const double *tile_sums, int local, double4 *rp, double4 *v,
+                            const double4 *f, int natoms, hipStream_t s);
 
 
 hipError_t launch_drift(const int32_t *atom_cluster, const ClusterState *st, double4 *rp, double4 *v,

@@ -174,6 +174,8 @@ PotConst make_pot(const scmd_sc_params &p) {
     pc.inv_rc_m = p.rc > 0.0 ? std::pow(p.rc, -(double)p.m) : 0.0;
     pc.inv_rc_n = p.rc > 0.0 ? std::pow(p.rc, -(double)p.n) : 0.0;
     pc.generic = (p.n == 9 && p.m == 6) ? 0 : 1;
+    pc.A8 = pc.A * 0.125;
+    pc.inv_rc_n512 = pc.inv_rc_n * 512.0;
     return pc;
 }
 
@@ -653,21 +655,32 @@ hipError_t enqueue_sweeps(scmd_ctx *c, hipStream_t s, bool capturing, int advanc
 hipError_t enqueue_forces(scmd_ctx *c, hipStream_t s, bool capturing, int advance) {
     hipError_t e = enqueue_sweeps(c, s, capturing, advance);
     if (e != hipSuccess) return e;
-    return launch_finalize(step_args(c, advance), c->d_tile_sums.p, c->nclusters, s);
+    return launch_finalize(step_args(c, advance), c->d_tile_sums.p, c->nclusters, advance, s);
 }
 
 // A run of nsteps velocity-Verlet steps; the last step of a captured run
-// carries the sampled profiling events.
+// carries the sampled profiling events.  A single cluster finishes each step
+// inside the next step's drift (k_drift_fin) and the run's last step with the
+// per-cluster finalize, which also stores the step counter; a batch runs the
+// finalize after every step.
 hipError_t enqueue_run(scmd_ctx *c, hipStream_t s, bool capturing, int64_t nsteps) {
     hipError_t e;
+    const bool fuse = c->nclusters == 1;
+    const StepArgs A = step_args(c, 1);
     for (int64_t k = 0; k < nsteps; ++k) {
-        e = launch_drift(c->atom_cluster.p, c->d_state.p, c->rp.p, c->v.p, c->f.p, c->natoms, c->dt, half_kick(c), s);
+        if (fuse && k > 0)
+            e = launch_drift_fin(A, c->d_tile_sums.p, (int)k, c->rp.p, c->v.p, c->f.p, c->natoms, s);
+        else
+            e = launch_drift(c->atom_cluster.p, c->d_state.p, c->rp.p, c->v.p, c->f.p, c->natoms, c->dt,
+                             half_kick(c), s);
         if (e != hipSuccess) return e;
         if (capturing) c->capture_sample = (k == nsteps - 1);
-        e = enqueue_forces(c, s, capturing, 1);
+        e = enqueue_sweeps(c, s, capturing, 1);
         if (e != hipSuccess) return e;
+        if (!fuse && (e = launch_finalize(A, c->d_tile_sums.p, c->nclusters, 1, s)) != hipSuccess) return e;
     }
     c->capture_sample = false;
+    if (fuse && nsteps > 0) return launch_finalize(A, c->d_tile_sums.p, c->nclusters, (int)nsteps, s);
     return hipSuccess;
 }
 

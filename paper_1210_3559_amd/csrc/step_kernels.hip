@@ -8,8 +8,7 @@
 // "Computational approach"); the thermostat factor of step k is applied at
 // the start of step k+1, which gives the same arithmetic as scaling the
 // velocities at the end of step k.
-#include "scmd_internal.h"
-#include "../../include/scmd.h"
+#include "sweep_common.h"
 
 namespace scmd {
 namespace {
@@ -22,6 +21,38 @@ __global__ __launch_bounds__(256) void k_drift(const int32_t *__restrict__ atom_
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= natoms) return;
     const double lam = st[atom_cluster[i]].lambda;
+    double4 vi = v[i];
+    const double4 fi = f[i];
+    double4 ri = rp[i];
+    vi.x = lam * vi.x;
+    vi.y = lam * vi.y;
+    vi.z = lam * vi.z;
+    vi.x = vi.x + h * fi.x;
+    vi.y = vi.y + h * fi.y;
+    vi.z = vi.z + h * fi.z;
+    ri.x = ri.x + dt * vi.x;
+    ri.y = ri.y + dt * vi.y;
+    ri.z = ri.z + dt * vi.z;
+    v[i] = vi;
+    rp[i] = ri;
+}
+
+// Drift fused with the finish of the previous step of a single cluster:
+// every workgroup reduces the cluster's tile sums itself (same order, so the
+// same thermostat factor in every workgroup) and workgroup 0 stores the
+// cluster state, which saves a launch per step.
+__global__ __launch_bounds__(256) void k_drift_fin(dev::FinalizeArgs fa, double4 *__restrict__ rp,
+                                                   double4 *__restrict__ v, const double4 *__restrict__ f,
+                                                   int natoms, double dt, double h) {
+#pragma clang fp contract(off)
+    __shared__ double sh[3 * 256];
+    __shared__ double lam_sh;
+    const double l0 = dev::cluster_finalize<256>(0, fa, sh, blockIdx.x == 0);
+    if (threadIdx.x == 0) lam_sh = l0;
+    __syncthreads();
+    const double lam = lam_sh;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= natoms) return;
     double4 vi = v[i];
     const double4 fi = f[i];
     double4 ri = rp[i];
@@ -56,6 +87,15 @@ hipError_t launch_drift(const int32_t *atom_cluster, const ClusterState *st, dou
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_drift, dim3((natoms + 255) / 256), dim3(256), 0, s, atom_cluster, st, rp, v, f, natoms,
                        dt, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_drift_fin(const StepArgs &a, const double *tile_sums, int local, double4 *rp, double4 *v,
+                            const double4 *f, int natoms, hipStream_t s) {
+    if (natoms <= 0) return hipSuccess;
+    const dev::FinalizeArgs fa{a.cd, a.st, tile_sums, a.flag, a.mass_u, a.dt, 1, local, 0};
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_drift_fin, dim3((natoms + 255) / 256), dim3(256), 0, s, fa, rp, v, f, natoms, a.dt, a.h);
     return hipGetLastError();
 }
 

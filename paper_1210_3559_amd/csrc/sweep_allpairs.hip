@@ -189,6 +189,8 @@ __global__ __launch_bounds__(64 * WI * WJ) void k_force(const SweepItem *__restr
     force_range<IPT, PREC, GEN, false>(xp, sg.a, sg.b, xi, yi, zi, ci, cif, gi, fx, fy, fz, eu, pc, Af);
     force_range<IPT, PREC, GEN, true>(xp, sg.b, sg.c, xi, yi, zi, ci, cif, gi, fx, fy, fz, eu, pc, Af);
     force_range<IPT, PREC, GEN, false>(xp, sg.c, sg.d, xi, yi, zi, ci, cif, gi, fx, fy, fz, eu, pc, Af);
+#pragma unroll
+    for (int p = 0; p < IPT; ++p) unscale_force<PREC, GEN>(fx[p], fy[p], fz[p], eu[p]);
 
     // combine the WJ wavefronts: sh_x[(w*4 + q)*TILE + li]
 #pragma unroll
@@ -313,8 +315,8 @@ __global__ __launch_bounds__(kRedBlock) void k_force_reduce(const ITile *__restr
 constexpr int kFinBlock = 256;
 
 __global__ __launch_bounds__(kFinBlock) void k_finalize(FinalizeArgs a) {
-    __shared__ double sh[kFinBlock];
-    cluster_finalize<kFinBlock>(blockIdx.x, a, sh);
+    __shared__ double sh[3 * kFinBlock];
+    cluster_finalize<kFinBlock>(blockIdx.x, a, sh, true);
 }
 
 template <int IPT, int WI, int WJ, int PREC, bool GEN>
@@ -409,9 +411,9 @@ hipError_t launch_force_reduce(const ITile *tiles, int ntiles, int tile, const S
     return reduce_dispatch(true, tiles, ntiles, tile, B, fo, pc, min_split, s);
 }
 
-hipError_t launch_finalize(const StepArgs &a, const double *tile_sums, int nclusters, hipStream_t s) {
+hipError_t launch_finalize(const StepArgs &a, const double *tile_sums, int nclusters, int step_add, hipStream_t s) {
     if (nclusters <= 0) return hipSuccess;
-    const FinalizeArgs fa{a.cd, a.st, tile_sums, a.flag, a.mass_u, a.dt, a.advance};
+    const FinalizeArgs fa{a.cd, a.st, tile_sums, a.flag, a.mass_u, a.dt, a.advance, step_add, 1};
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_finalize, dim3(nclusters), dim3(kFinBlock), 0, s, fa);
     return hipGetLastError();

@@ -95,7 +95,40 @@ __device__ __forceinline__ void density_pair(double dx, double dy, double dz, bo
 // Force and pair-energy terms:
 //   F_i += u^(m+2) [A u^(n-m) - P_i - P_j] (r_i - r_j),  eu += u^n (- rc^-n).
 // ci = -P_i, pj = P_j (single-precision copies for the mixed form).
+//
+// The FP64 (n, m) = (9, 6) form works with w = 2u: the Newton step for
+// 1/sqrt(r^2) written without its factor 1/2, w = y (3 - r^2 y^2), is exactly
+// twice y (3/2 - (r^2/2) y^2) (scaling by 2 commutes with rounding), so one
+// multiply per pair drops out.  With A/8 in place of A every later product
+// is an exact power-of-two multiple of the unscaled one: the force sums come
+// out 2^8 and the u^n sums 2^9 times too large, and unscale_force() divides
+// them out once per sum.  The results are bitwise those of the form with u.
 // ---------------------------------------------------------------------------
+template <int PREC, bool GEN>
+struct ForceScale {
+    static constexpr double f = 1.0, e = 1.0;
+};
+template <>
+struct ForceScale<SCMD_FP64, false> {
+    static constexpr double f = 1.0 / 256.0, e = 1.0 / 512.0;
+};
+
+template <int PREC, bool GEN>
+__device__ __forceinline__ void unscale_force(double &fx, double &fy, double &fz, double &eu) {
+    if constexpr (ForceScale<PREC, GEN>::f != 1.0) {
+        fx *= ForceScale<PREC, GEN>::f;
+        fy *= ForceScale<PREC, GEN>::f;
+        fz *= ForceScale<PREC, GEN>::f;
+        eu *= ForceScale<PREC, GEN>::e;
+    }
+}
+
+// 2/sqrt(x) from the hardware estimate and one Newton step (see above).
+__device__ __forceinline__ double rsq2_nr(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    return y * __builtin_fma(-x, y * y, 3.0);
+}
+
 template <int PREC, bool GEN, bool MASK, bool CUT>
 __device__ __forceinline__ void force_pair(double dx, double dy, double dz, bool self, double ci, double pj,
                                            float cif, float pjf, double &fx, double &fy, double &fz, double &eu,
@@ -106,17 +139,18 @@ __device__ __forceinline__ void force_pair(double dx, double dy, double dz, bool
         if constexpr (CUT) off = !(r2 < pc.rc2);
         if constexpr (MASK) off = off || self;
         if constexpr (MASK || CUT) r2 = off ? kSelfR2 : r2;
-        double u = rsq_nr(r2);
         double f, un;
         if constexpr (!GEN) {
-            double u2 = u * u;
-            double u3 = u2 * u;
-            double u4 = u2 * u2;
-            double u8 = u4 * u4;
-            double q = __builtin_fma(pc.A, u3, ci) - pj;
-            f = u8 * q;
-            un = u8 * u;
+            const double w = rsq2_nr(r2);  // 2u
+            const double w2 = w * w;
+            const double w3 = w2 * w;
+            const double w4 = w2 * w2;
+            const double w8 = w4 * w4;
+            const double q = __builtin_fma(pc.A8, w3, ci) - pj;
+            f = w8 * q;   // 2^8 x the force coefficient
+            un = w8 * w;  // 2^9 u^n
         } else {
+            double u = rsq_nr(r2);
             double um2 = powi(u, pc.m + 2);
             double und = powi(u, pc.n - pc.m);
             double q = __builtin_fma(pc.A, und, ci) - pj;
@@ -127,7 +161,7 @@ __device__ __forceinline__ void force_pair(double dx, double dy, double dz, bool
         fy = __builtin_fma(f, dy, fy);
         fz = __builtin_fma(f, dz, fz);
         if constexpr (CUT) {
-            eu += off ? 0.0 : un - pc.inv_rc_n;
+            eu += off ? 0.0 : un - (GEN ? pc.inv_rc_n : pc.inv_rc_n512);
         } else {
             eu += un;
         }
@@ -242,6 +276,8 @@ struct FinalizeArgs {
     int *flag;
     double mass_u, dt;
     int advance;
+    int step_add;    // completed steps since st.step was last stored (ramp index = st.step + step_add)
+    int store_step;  // 1: store st.step + step_add
 };
 
 // Finish one atom of the force sweep: store F and the site pair energy,
@@ -262,11 +298,40 @@ __device__ __forceinline__ void force_atom(int i, double fx, double fy, double f
     v2 += vi.x * vi.x + vi.y * vi.y + vi.z * vi.z;
 }
 
-// Per-cluster finish, run by one whole workgroup per cluster: fixed-order
-// sums of the tile sums, then temperature and the Berendsen factor.
-// Returns the cluster's current thermostat factor to thread 0.
+// Three fixed-shape tree sums at once (same order as block_sum for each).
+// sh needs 3 * BLOCK doubles.  Every thread of the workgroup must call it.
 template <int BLOCK>
-__device__ double cluster_finalize(int c, const FinalizeArgs &o, double *sh) {
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = a;
+    sh[BLOCK + t] = b;
+    sh[2 * BLOCK + t] = c;
+    __syncthreads();
+#pragma unroll
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            sh[t] += sh[t + s];
+            sh[BLOCK + t] += sh[BLOCK + t + s];
+            sh[2 * BLOCK + t] += sh[2 * BLOCK + t + s];
+        }
+        __syncthreads();
+    }
+    a = sh[0];
+    b = sh[BLOCK];
+    c = sh[2 * BLOCK];
+    __syncthreads();
+}
+
+// Per-cluster finish, run by one whole workgroup: fixed-order sums of the
+// tile sums, then temperature and the Berendsen factor.  Every workgroup that
+// runs it for the same cluster and arguments gets the same result bit for
+// bit; only a `writer` stores the cluster state (st.step only with
+// store_step).  Returns the cluster's current thermostat factor to thread 0.
+// sh needs 3 * BLOCK doubles.
+template <int BLOCK>
+__device__ double cluster_finalize(int c, const FinalizeArgs &o, double *sh, bool writer) {
+    // no contraction: the same rounding in every kernel that inlines this
+#pragma clang fp contract(off)
     const ClusterDesc d = o.cd[c];
     double emb = 0.0, epair = 0.0, v2 = 0.0;
     for (int t = threadIdx.x; t < d.ntiles; t += BLOCK) {
@@ -275,22 +340,21 @@ __device__ double cluster_finalize(int c, const FinalizeArgs &o, double *sh) {
         epair += ts[1];
         v2 += ts[2];
     }
-    emb = block_sum<BLOCK>(emb, sh);
-    epair = block_sum<BLOCK>(epair, sh);
-    v2 = block_sum<BLOCK>(v2, sh);
+    block_sum3<BLOCK>(emb, epair, v2, sh);
     if (threadIdx.x != 0) return 1.0;
     ClusterState s = o.st[c];
     const double ke = 0.5 * o.mass_u * v2 * kEvPerUA2Fs2;
     const double T = d.ndof > 0 ? 2.0 * ke / ((double)d.ndof * kBoltzmannEv) : 0.0;
     double lam = s.lambda;
+    const int64_t step_now = s.step + o.step_add;
+    if (o.store_step) s.step = step_now;
     if (o.advance) {
-        s.step += 1;
         lam = 1.0;
         s.ttarget = 0.0;
         if (d.kind == SCMD_BERENDSEN) {
             double tt = d.T_end;
             if (d.ramp > 0) {
-                const int64_t k = s.step < d.ramp ? s.step : d.ramp;
+                const int64_t k = step_now < d.ramp ? step_now : d.ramp;
                 tt = d.T_start + (d.T_end - d.T_start) * (double)k / (double)d.ramp;
             }
             s.ttarget = tt;
@@ -306,9 +370,9 @@ __device__ double cluster_finalize(int c, const FinalizeArgs &o, double *sh) {
     s.temp = lam * lam * T;
     if (!isfinite(s.epot) || !isfinite(s.ekin)) {
         s.nonfinite = 1;
-        atomicOr(o.flag, 1);
+        if (writer) atomicOr(o.flag, 1);
     }
-    o.st[c] = s;
+    if (writer) o.st[c] = s;
     return s.lambda;
 }
 

@@ -232,6 +232,7 @@ __global__ __launch_bounds__(64 * W) void k_row_force(const ITile *__restrict__ 
     plain(L.k_full);
     masked(L.k_end);
 
+    unscale_force<PREC, GEN>(fx, fy, fz, eu);
     double v[4] = {fx, fy, fz, eu};
     row_reduce<W, 4>(L, v, sh);
     double epair = 0.0, v2 = 0.0;

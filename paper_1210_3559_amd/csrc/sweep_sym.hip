@@ -73,15 +73,16 @@ __device__ __forceinline__ void sym_force_pair(double dx, double dy, double dz, 
                                                double &gx, double &gy, double &gz, const PotConst &pc, float Af) {
     double f, un;
     if constexpr (PREC == SCMD_FP64) {
+        // w = 2u; sums scaled by 2^8 (force) and 2^9 (u^n), see force_pair
         const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
-        const double u = rsq_nr(r2);
-        const double u2 = u * u;
-        const double u3 = u2 * u;
-        const double u4 = u2 * u2;
-        const double u8 = u4 * u4;
-        const double q = __builtin_fma(pc.A, u3, ci) - pj;
-        f = u8 * q;
-        un = u8 * u;
+        const double w = rsq2_nr(r2);
+        const double w2 = w * w;
+        const double w3 = w2 * w;
+        const double w4 = w2 * w2;
+        const double w8 = w4 * w4;
+        const double q = __builtin_fma(pc.A8, w3, ci) - pj;
+        f = w8 * q;
+        un = w8 * w;
     } else {
         const double r2d = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
         const float u = __builtin_amdgcn_rsqf((float)r2d);
@@ -161,6 +162,8 @@ __global__ __launch_bounds__(64) void k_sym_force(const SymItem *__restrict__ it
                 gy = ror1(gy);
                 gz = ror1(gz);
             }
+            double ge = 0.0;
+            unscale_force<PREC, false>(gx, gy, gz, ge);
             double *out = jpart + ((size_t)(t.jbase + it.g) * 3) * 64 + lane;
             out[0] = gx;
             out[64] = gy;
@@ -169,6 +172,8 @@ __global__ __launch_bounds__(64) void k_sym_force(const SymItem *__restrict__ it
 #pragma unroll
         for (int p = 0; p < IPT; ++p) eu[p] *= 2.0;  // each unordered pair once
     }
+#pragma unroll
+    for (int p = 0; p < IPT; ++p) unscale_force<PREC, false>(fx[p], fy[p], fz[p], eu[p]);
     double *out = ipart + (size_t)it.slot * 4 * 64 * IPT;
 #pragma unroll
     for (int p = 0; p < IPT; ++p) {
