@@ -122,10 +122,10 @@ typedef struct {
                   pair evaluated once, j tiles rotated through the wavefront;
                   ipt 2 or 4, waves_i and waves_j ignored; (n, m) = (9, 6) and
                   all-pairs only); 3 = row sweeps (one workgroup of
-                  64 * waves_j threads per run of at most 64 atoms against all
-                  of its partners, finished in the same launch; waves_j 4, 8
-                  or 16 (0 = 16), target_items = workgroups per sweep (0 =
-                  256), ipt and waves_i ignored; all-pairs only) */
+                  64 * waves_j threads per run of at most 8 * waves_j atoms
+                  against all of its partners, finished in the same launch;
+                  waves_j 4, 8 or 16 (0 = 8), target_items = workgroups per
+                  sweep (0 = 256), ipt and waves_i ignored; all-pairs only) */
 } scmd_tuning;
 
 /* Kernel classes timed by scmd_get_kernel_time (device time per launch). */

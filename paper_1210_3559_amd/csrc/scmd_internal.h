@@ -170,12 +170,27 @@ struct RowLaunch {
     const int32_t *order;  // launch order of the tiles
     const ClusterDesc *cd;
     int ntiles;
-    int waves;             // 4, 8 or 16
+    int waves;             // 4, 8 or 16; tiles hold at most 8 * waves atoms
+    int nmax;              // atoms of the largest cluster (LDS staging when <= kRowStageMax)
+    // single cluster with equal runs: tile b = atoms [off + b ni, min(off + n,
+    // off + (b+1) ni)) of cluster 0, computed without reading the tables
+    int uni_off, uni_n, uni_ni;  // uni_ni = 0: use the tables
 };
-hipError_t launch_row_density(const RowLaunch &L, const SweepBuffers &B, const PotConst &pc, int precision,
-                              hipStream_t s);
-hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, const PotConst &pc,
-                            int precision, hipStream_t s);
+constexpr int kRowStageMax = 4096;  // clusters up to this size are staged in LDS (128 KiB)
+// Drift folded into the row density sweep of a single staged cluster: every
+// workgroup drifts the whole cluster while staging it (r + dt (lambda v +
+// h F)); mode 2 first finishes the previous step's thermostat factor from its
+// v^2 tile sums (the finalize's order, so the same bits) and workgroup 0
+// stores it in st->lambda for the force sweep, whose epilogue (fused = 1)
+// applies lambda and the first half-kick and stores the positions.
+struct RowDrift {
+    int mode;   // 0: positions as they are; 1: drift with st->lambda; 2: new lambda, then drift
+    int local;  // mode 2: steps completed in this run (ramp index st->step + local)
+};
+hipError_t launch_row_density(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, const RowDrift &dr,
+                              const PotConst &pc, int precision, hipStream_t s);
+hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, int fused,
+                            const PotConst &pc, int precision, hipStream_t s);
 
 // Per-cluster energies, temperature and thermostat factor from the tile sums;
 // step_add = steps completed since the cluster step counter was last stored

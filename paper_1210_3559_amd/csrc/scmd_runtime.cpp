@@ -100,6 +100,8 @@ struct scmd_ctx {
     // symmetric all-pairs plan
     bool row = false;       // row sweeps (small clusters, no partial slots)
     int row_waves = 16;
+    int row_uni_off = 0, row_uni_n = 0, row_uni_ni = 0;  // single-cluster row plan (ni = 0: tables)
+    int row_nmax = 0;
     bool sym = false;
     int sym_ipt = 4, sym_nitems = 0, sym_ntiles = 0;
     DevBuf<SymItem> d_sitems;
@@ -350,14 +352,18 @@ int build_sym_plan(scmd_ctx *c, int target) {
     return SCMD_OK;
 }
 
-// Row plan: tiles of ni <= 64 atoms, one workgroup each, sized so that the
-// sweep has about `target` workgroups of about equal work (ni n_c).
+// Row plan: tiles of ni <= 8 * waves atoms, one workgroup each, sized so
+// that the sweep has about `target` workgroups of about equal work (ni n_c).
 int build_row_plan(scmd_ctx *c, int target, std::vector<ITile> *tiles_out) {
     double total = 0.0;
+    int nmax = 0;
     for (int k = 0; k < c->nclusters; ++k) {
         const double n = (double)(c->offsets[k + 1] - c->offsets[k]);
         total += n * n;
+        nmax = std::max(nmax, (int)(c->offsets[k + 1] - c->offsets[k]));
     }
+    c->row_nmax = nmax;
+    const double ni_cap = std::min(64, 8 * c->row_waves);
     const double wstar = std::max(1.0, total / std::max(1, target));
     std::vector<ITile> tiles;
     int tmax = 1;
@@ -365,7 +371,7 @@ int build_row_plan(scmd_ctx *c, int target, std::vector<ITile> *tiles_out) {
         ClusterDesc &d = c->cdesc[k];
         const int off = (int)c->offsets[k];
         const int n = (int)(c->offsets[k + 1] - c->offsets[k]);
-        const int ni = n > 0 ? (int)std::min<double>(64.0, std::max(1.0, std::ceil(wstar / n))) : 1;
+        const int ni = n > 0 ? (int)std::min<double>(ni_cap, std::max(1.0, std::ceil(wstar / n))) : 1;
         d.off = off;
         d.n = n;
         d.tile0 = (int)tiles.size();
@@ -392,6 +398,12 @@ int build_row_plan(scmd_ctx *c, int target, std::vector<ITile> *tiles_out) {
     c->tile = tmax;
     c->nitems = 0;
     c->ntiles = (int)tiles.size();
+    c->row_uni_ni = 0;
+    if (c->nclusters == 1 && !tiles.empty()) {
+        c->row_uni_off = c->cdesc[0].off;
+        c->row_uni_n = c->cdesc[0].n;
+        c->row_uni_ni = tiles[0].ni;
+    }
     c->has_split = false;
     HIP_TRY(c, c->d_items.ensure(1));
     HIP_TRY(c, c->d_order.ensure(std::max<size_t>(order.size(), 1)));
@@ -431,7 +443,7 @@ int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
         if (c->neighbour == SCMD_ALLPAIRS && (c->tuning.pairs == 3 || (c->tuning.pairs == 0 && row_default))) {
             c->sym = false;
             c->row = true;
-            c->row_waves = c->tuning.waves_j > 0 ? c->tuning.waves_j : 16;
+            c->row_waves = c->tuning.waves_j > 0 ? c->tuning.waves_j : 8;
             return build_row_plan(c, c->tuning.target_items > 0 ? c->tuning.target_items : 256, tiles_out);
         }
         c->sym = allowed && (c->tuning.pairs == 2 || (c->tuning.pairs == 0 && (batch || nmax > 4096)));
@@ -586,7 +598,11 @@ SweepBuffers buffers(scmd_ctx *c) {
     return SweepBuffers{c->rp.p, c->xp.p, c->f.p, c->v.p, c->rho.p, c->d_part.p, c->d_tile_sums.p};
 }
 
-hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int advance) {
+// One pair sweep (with its profiling events).  Row sweeps of one staged
+// cluster take the drift (drift_mode, local: RowDrift) and the fused force
+// epilogue.
+hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int advance, int drift_mode = 0,
+                 int local = 0, int fused = 0) {
     int ev = -1;
     if (c->profiling && (!capturing || (c->graph_events_ok && c->capture_sample))) {
         ev = take_event(c, force ? SCMD_KERNEL_FORCE : SCMD_KERNEL_DENSITY);
@@ -604,8 +620,10 @@ hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int adv
         e = force ? launch_sym_force(L, B, A, c->pc, c->precision, 0, s)
                   : launch_sym_density(L, B, c->pc, c->precision, 0, s);
     } else if (c->row) {
-        const RowLaunch R{c->d_tiles.p, c->d_order.p, c->d_cdesc.p, c->ntiles, c->row_waves};
-        e = force ? launch_row_force(R, B, A, c->pc, c->precision, s) : launch_row_density(R, B, c->pc, c->precision, s);
+        const RowLaunch R{c->d_tiles.p, c->d_order.p, c->d_cdesc.p, c->ntiles, c->row_waves, c->row_nmax,
+                          c->row_uni_off, c->row_uni_n, c->row_uni_ni};
+        e = force ? launch_row_force(R, B, A, fused, c->pc, c->precision, s)
+                  : launch_row_density(R, B, A, RowDrift{drift_mode, local}, c->pc, c->precision, s);
     } else if (c->neighbour == SCMD_CELLLIST) {
         e = force ? cell_list_force(c->cells, B, A, c->d_tiles.p, c->ntiles, c->tile, c->pc, c->precision, s)
                   : cell_list_density(c->cells, B, c->d_tiles.p, c->ntiles, c->tile, c->pc, c->precision, s);
@@ -665,8 +683,21 @@ hipError_t enqueue_forces(scmd_ctx *c, hipStream_t s, bool capturing, int advanc
 // finalize after every step.
 hipError_t enqueue_run(scmd_ctx *c, hipStream_t s, bool capturing, int64_t nsteps) {
     hipError_t e;
-    const bool fuse = c->nclusters == 1;
     const StepArgs A = step_args(c, 1);
+    if (c->row && c->nclusters == 1 && c->row_nmax <= kRowStageMax && c->natoms > 0) {
+        // two launches per step: the density sweep drifts the staged cluster
+        // (after finishing the previous step's thermostat factor), the force
+        // sweep's epilogue kicks and stores the positions
+        for (int64_t k = 0; k < nsteps; ++k) {
+            if (capturing) c->capture_sample = (k == nsteps - 1);
+            if ((e = sweep(c, false, s, capturing, 1, k == 0 ? 1 : 2, (int)k)) != hipSuccess) return e;
+            if ((e = sweep(c, true, s, capturing, 1, 0, 0, 1)) != hipSuccess) return e;
+        }
+        c->capture_sample = false;
+        if (nsteps > 0) return launch_finalize(A, c->d_tile_sums.p, c->nclusters, (int)nsteps, s);
+        return hipSuccess;
+    }
+    const bool fuse = c->nclusters == 1;
     for (int64_t k = 0; k < nsteps; ++k) {
         if (fuse && k > 0)
             e = launch_drift_fin(A, c->d_tile_sums.p, (int)k, c->rp.p, c->v.p, c->f.p, c->natoms, s);

@@ -45,9 +45,9 @@ __global__ __launch_bounds__(256) void k_drift_fin(dev::FinalizeArgs fa, double4
                                                    double4 *__restrict__ v, const double4 *__restrict__ f,
                                                    int natoms, double dt, double h) {
 #pragma clang fp contract(off)
-    __shared__ double sh[3 * 256];
+    __shared__ double sh[12];
     __shared__ double lam_sh;
-    const double l0 = dev::cluster_finalize<256>(0, fa, sh, blockIdx.x == 0);
+    const double l0 = dev::cluster_finalize(0, fa, sh, blockIdx.x == 0);
     if (threadIdx.x == 0) lam_sh = l0;
     __syncthreads();
     const double lam = lam_sh;

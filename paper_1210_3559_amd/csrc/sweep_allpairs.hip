@@ -315,8 +315,8 @@ __global__ __launch_bounds__(kRedBlock) void k_force_reduce(const ITile *__restr
 constexpr int kFinBlock = 256;
 
 __global__ __launch_bounds__(kFinBlock) void k_finalize(FinalizeArgs a) {
-    __shared__ double sh[3 * kFinBlock];
-    cluster_finalize<kFinBlock>(blockIdx.x, a, sh, true);
+    __shared__ double sh[12];
+    cluster_finalize(blockIdx.x, a, sh, true);
 }
 
 template <int IPT, int WI, int WJ, int PREC, bool GEN>

@@ -250,15 +250,20 @@ struct DensityOut {
     double *tile_sums;
 };
 
-// Finish one atom of the density sweep from its complete sum of u^m.
-__device__ __forceinline__ double density_atom(int i, double s, const DensityOut &o, const PotConst &pc) {
+// Finish one atom of the density sweep from its complete sum of u^m; q is
+// its position.
+__device__ __forceinline__ double density_atom_at(int i, double s, const double4 &q, const DensityOut &o,
+                                                  const PotConst &pc) {
     const double r = pc.am * s;
     const double sq = sqrt(r);
     const double psi = r > 0.0 ? 1.0 / sq : 0.0;
-    const double4 q = o.rp[i];
     o.rho[i] = r;
     o.xp[i] = make_double4(q.x, q.y, q.z, pc.Pscale * psi);
     return -pc.eps_c * sq;  // embedding energy of atom i
+}
+
+__device__ __forceinline__ double density_atom(int i, double s, const DensityOut &o, const PotConst &pc) {
+    return density_atom_at(i, s, o.rp[i], o, pc);
 }
 
 struct ForceOut {
@@ -267,6 +272,12 @@ struct ForceOut {
     double *tile_sums;
     double h;
     int advance;
+    // row sweeps of a single cluster whose drift ran inside the density
+    // sweep: the force epilogue also applies the thermostat factor st->lambda
+    // and the first half-kick, and stores the drifted positions in rp
+    int fused;
+    const ClusterState *st;
+    double4 *rp;
 };
 
 struct FinalizeArgs {
@@ -282,12 +293,12 @@ struct FinalizeArgs {
 
 // Finish one atom of the force sweep: store F and the site pair energy,
 // second half-kick when advancing; returns (pair energy, v^2) through refs.
-__device__ __forceinline__ void force_atom(int i, double fx, double fy, double fz, double eu, const ForceOut &o,
-                                           const PotConst &pc, double &epair, double &v2) {
+// vi is the atom's current velocity.
+__device__ __forceinline__ void force_atom_v(int i, double fx, double fy, double fz, double eu, double4 vi,
+                                             const ForceOut &o, const PotConst &pc, double &epair, double &v2) {
 #pragma clang fp contract(off)
     const double ei = pc.half_eps_an * eu;
     o.f[i] = make_double4(fx, fy, fz, ei);
-    double4 vi = o.v[i];
     if (o.advance) {
         vi.x = vi.x + o.h * fx;
         vi.y = vi.y + o.h * fy;
@@ -298,76 +309,112 @@ __device__ __forceinline__ void force_atom(int i, double fx, double fy, double f
     v2 += vi.x * vi.x + vi.y * vi.y + vi.z * vi.z;
 }
 
-// Three fixed-shape tree sums at once (same order as block_sum for each).
-// sh needs 3 * BLOCK doubles.  Every thread of the workgroup must call it.
-template <int BLOCK>
-__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *sh) {
-    const int t = threadIdx.x;
-    sh[t] = a;
-    sh[BLOCK + t] = b;
-    sh[2 * BLOCK + t] = c;
-    __syncthreads();
-#pragma unroll
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (t < s) {
-            sh[t] += sh[t + s];
-            sh[BLOCK + t] += sh[BLOCK + t + s];
-            sh[2 * BLOCK + t] += sh[2 * BLOCK + t + s];
+__device__ __forceinline__ void force_atom(int i, double fx, double fy, double fz, double eu, const ForceOut &o,
+                                           const PotConst &pc, double &epair, double &v2) {
+    force_atom_v(i, fx, fy, fz, eu, o.v[i], o, pc, epair, v2);
+}
+
+// Kinetic energy (eV) and temperature of a cluster from its sum of v^2.
+struct KinT {
+    double ke, T;
+};
+__device__ __forceinline__ KinT kinetic_temperature(const ClusterDesc &d, double mass_u, double v2) {
+#pragma clang fp contract(off)
+    const double ke = 0.5 * mass_u * v2 * kEvPerUA2Fs2;
+    const double T = d.ndof > 0 ? 2.0 * ke / ((double)d.ndof * kBoltzmannEv) : 0.0;
+    return KinT{ke, T};
+}
+
+// Thermostat factor after a step whose ramp index is step_now, at
+// temperature T; *ttarget receives the target (0 without thermostat).
+__device__ __forceinline__ double thermostat_lambda(const ClusterDesc &d, double dt, double T, int64_t step_now,
+                                                    double *ttarget) {
+#pragma clang fp contract(off)
+    double lam = 1.0;
+    *ttarget = 0.0;
+    if (d.kind == SCMD_BERENDSEN) {
+        double tt = d.T_end;
+        if (d.ramp > 0) {
+            const int64_t k = step_now < d.ramp ? step_now : d.ramp;
+            tt = d.T_start + (d.T_end - d.T_start) * (double)k / (double)d.ramp;
         }
-        __syncthreads();
+        *ttarget = tt;
+        if (T > 0.0) {
+            const double x = 1.0 + (dt / d.tau) * (tt / T - 1.0);
+            lam = x > 0.0 ? sqrt(x) : 0.0;
+        }
     }
-    a = sh[0];
-    b = sh[BLOCK];
-    c = sh[2 * BLOCK];
+    return lam;
+}
+
+// Fixed-order totals of a cluster's tile sums: threads 0..255 add every
+// 256th tile, each of the four wavefronts folds its lanes with an xor
+// butterfly (the value of lane 0 is used), and the four wavefront sums are
+// added as (w0 + w1) + (w2 + w3).  Any workgroup of >= 256 threads gets the
+// same bits; every thread must call it.  sh needs 12 doubles.  With V2_ONLY
+// only the v^2 column is read (the others come back as 0).
+constexpr int kTotBlock = 256;
+template <bool V2_ONLY>
+__device__ __forceinline__ void cluster_totals(const ClusterDesc &d, const double *tile_sums, double *sh,
+                                               double &emb, double &epair, double &v2) {
+    emb = epair = v2 = 0.0;
+    const int t = threadIdx.x;
+    if (t < kTotBlock) {
+        for (int k = t; k < d.ntiles; k += kTotBlock) {
+            const double *ts = tile_sums + (size_t)(d.tile0 + k) * kTileSums;
+            if constexpr (!V2_ONLY) {
+                emb += ts[0];
+                epair += ts[1];
+            }
+            v2 += ts[2];
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        if constexpr (!V2_ONLY) {
+            emb += __shfl_xor(emb, o, 64);
+            epair += __shfl_xor(epair, o, 64);
+        }
+        v2 += __shfl_xor(v2, o, 64);
+    }
+    if (t < kTotBlock && (t & 63) == 0) {
+        const int w = t >> 6;
+        sh[w] = emb;
+        sh[4 + w] = epair;
+        sh[8 + w] = v2;
+    }
+    __syncthreads();
+    emb = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    epair = (sh[4] + sh[5]) + (sh[6] + sh[7]);
+    v2 = (sh[8] + sh[9]) + (sh[10] + sh[11]);
     __syncthreads();
 }
 
-// Per-cluster finish, run by one whole workgroup: fixed-order sums of the
-// tile sums, then temperature and the Berendsen factor.  Every workgroup that
-// runs it for the same cluster and arguments gets the same result bit for
-// bit; only a `writer` stores the cluster state (st.step only with
-// store_step).  Returns the cluster's current thermostat factor to thread 0.
-// sh needs 3 * BLOCK doubles.
-template <int BLOCK>
-__device__ double cluster_finalize(int c, const FinalizeArgs &o, double *sh, bool writer) {
+// Per-cluster finish, run by one whole workgroup (>= 256 threads): the
+// totals of the tile sums, then temperature and the Berendsen factor.  Every
+// workgroup that runs it for the same cluster and arguments gets the same
+// result bit for bit; only a `writer` stores the cluster state (st.step only
+// with store_step).  Returns the cluster's current thermostat factor to
+// thread 0.  sh needs 12 doubles.
+__device__ inline double cluster_finalize(int c, const FinalizeArgs &o, double *sh, bool writer) {
     // no contraction: the same rounding in every kernel that inlines this
 #pragma clang fp contract(off)
     const ClusterDesc d = o.cd[c];
-    double emb = 0.0, epair = 0.0, v2 = 0.0;
-    for (int t = threadIdx.x; t < d.ntiles; t += BLOCK) {
-        const double *ts = o.tile_sums + (size_t)(d.tile0 + t) * kTileSums;
-        emb += ts[0];
-        epair += ts[1];
-        v2 += ts[2];
-    }
-    block_sum3<BLOCK>(emb, epair, v2, sh);
+    double emb, epair, v2;
+    cluster_totals<false>(d, o.tile_sums, sh, emb, epair, v2);
     if (threadIdx.x != 0) return 1.0;
     ClusterState s = o.st[c];
-    const double ke = 0.5 * o.mass_u * v2 * kEvPerUA2Fs2;
-    const double T = d.ndof > 0 ? 2.0 * ke / ((double)d.ndof * kBoltzmannEv) : 0.0;
+    const KinT kt = kinetic_temperature(d, o.mass_u, v2);
     double lam = s.lambda;
     const int64_t step_now = s.step + o.step_add;
     if (o.store_step) s.step = step_now;
     if (o.advance) {
-        lam = 1.0;
-        s.ttarget = 0.0;
-        if (d.kind == SCMD_BERENDSEN) {
-            double tt = d.T_end;
-            if (d.ramp > 0) {
-                const int64_t k = step_now < d.ramp ? step_now : d.ramp;
-                tt = d.T_start + (d.T_end - d.T_start) * (double)k / (double)d.ramp;
-            }
-            s.ttarget = tt;
-            if (T > 0.0) {
-                const double x = 1.0 + (o.dt / d.tau) * (tt / T - 1.0);
-                lam = x > 0.0 ? sqrt(x) : 0.0;
-            }
-        }
+        lam = thermostat_lambda(d, o.dt, kt.T, step_now, &s.ttarget);
         s.lambda = lam;
     }
     s.epot = emb + epair;
-    s.ekin = lam * lam * ke;
-    s.temp = lam * lam * T;
+    s.ekin = lam * lam * kt.ke;
+    s.temp = lam * lam * kt.T;
     if (!isfinite(s.epot) || !isfinite(s.ekin)) {
         s.nonfinite = 1;
         if (writer) atomicOr(o.flag, 1);

@@ -5,14 +5,21 @@
 // The two sweeps are those of the paper's scheme (Sec. 2 "Computational
 // approach": the density sums of Eq. (rho), then the forces of Eq. (SC)),
 // evaluated one-sidedly: every atom accumulates its own sums.  A workgroup
-// of 64*W threads owns atoms [i0, i0 + ni) of one cluster, ni <= 64.
-// Thread t works for atom il = t % ni on partner stream s = t / ni; the S =
-// floor(64 W / ni) streams of an atom interleave over the cluster (stream s
-// visits j = off + s, off + s + S, ...), so almost every thread is busy for
-// any ni and consecutive threads load neighbouring partners.  The partner
-// window [i0, i0 + ni), which holds the self pairs, and the last, partly
-// filled round of each wavefront are the only masked iterations.  Stream
-// sums are combined in LDS in a fixed order (deterministic), and the
+// of 64*W threads owns atoms [i0, i0 + ni) of one cluster, ni <= 8 W.
+//
+// Threads form groups of 8 consecutive lanes; group g works for atom
+// il = g % ni, and its lanes run the partner streams s = 8 (g / ni) + lane8,
+// s < S = 8 floor(8 W / ni).  Stream s visits j = off + s, off + s + S, ...,
+// so the S streams of an atom interleave over the whole cluster and the 8
+// lanes of a group read 8 neighbouring partners.  The partner window
+// [i0, i0 + ni), which holds the self pairs, and the last, partly filled
+// round of each wavefront are the only masked iterations.
+//
+// When the cluster fits (at most kRowStageMax atoms), the workgroup first
+// copies the cluster's positions into LDS (each thread issues all of its
+// loads before storing any), so the pair loop reads LDS only.  Stream sums are added across
+// the 8 lanes of a group with DPP (quad_perm, row_half_mirror), then across
+// groups through LDS in a fixed order: the result is deterministic.  The
 // workgroup then finishes its atoms: psi and the embedding energy after the
 // density sweep, F, the second half-kick and the energy / v^2 sums after the
 // force sweep.
@@ -28,35 +35,38 @@ __device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b :
 
 // Thread layout of a row workgroup and the wave-uniform round ranges.
 struct RowLayout {
-    int ni, S, il, s, i;
-    bool active;
+    int ni, G, S;      // atoms, groups per atom, streams per atom (8 G)
+    int il, s, i;      // this thread's atom (local, global) and stream
+    bool active;       // this thread's group works for an atom
     int k_mask0, k_mask1;  // rounds [k_mask0, k_mask1) may meet the self window
     int k_full, k_end;     // rounds [0, k_full) are full for the whole wavefront; k_end: last round + 1
 };
 
 template <int W>
-__device__ __forceinline__ RowLayout row_layout(const ITile &t, int off, int n) {
+__device__ __forceinline__ RowLayout row_layout(int i0, int ni, int off, int n) {
+    constexpr int NG = 8 * W;  // groups in the workgroup
     RowLayout L;
-    L.ni = t.ni;
-    L.S = (64 * W) / L.ni;
+    L.ni = ni;
+    L.G = NG / ni;
+    L.S = 8 * L.G;
     const int tid = threadIdx.x;
+    const int grp = tid >> 3, lane8 = tid & 7;
+    const int nact = ni * L.G;  // active groups
+    L.active = grp < nact;
+    // idle groups shadow the last active group (valid addresses, results dropped)
+    const int gg = L.active ? grp : nact - 1;
+    L.il = gg % ni;
+    L.s = 8 * (gg / ni) + lane8;
+    L.i = i0 + L.il;
+    // stream range of this wavefront (wave-uniform): groups 8w .. 8w+7
     const int wave = tid >> 6;
-    L.active = tid < L.ni * L.S;
-    // idle threads shadow the last stream (valid addresses, results dropped)
-    const int tt = L.active ? tid : L.ni * L.S - 1;
-    L.il = tt % L.ni;
-    L.s = tt / L.ni;
-    L.i = t.i0 + L.il;
-    // stream range of this wavefront (wave-uniform)
-    const int t_lo = wave * 64;
-    const int t_hi = min(wave * 64 + 63, L.ni * L.S - 1);
-    const int s_min = min(t_lo, L.ni * L.S - 1) / L.ni;
-    const int s_max = t_hi / L.ni;
+    const int g_lo = min(8 * wave, nact - 1), g_hi = min(8 * wave + 7, nact - 1);
+    const int s_min = 8 * (g_lo / ni), s_max = 8 * (g_hi / ni) + 7;
     // rounds in which some thread of the wavefront meets j in [i0, i0 + ni)
-    const int w0 = t.i0 - off, w1 = t.i0 + L.ni - 1 - off;
+    const int w0 = i0 - off, w1 = i0 + ni - 1 - off;
     const int klo = max(0, floor_div(w0 - s_max + L.S - 1, L.S));
     const int khi = floor_div(w1 - s_min, L.S);  // inclusive
-    // rounds: thread with stream s has ceil((n - s) / S) of them
+    // rounds: a thread with stream s has ceil((n - s) / S) of them
     L.k_full = n > s_max ? (n - s_max + L.S - 1) / L.S : 0;
     L.k_end = n > s_min ? (n - s_min + L.S - 1) / L.S : 0;
     L.k_mask0 = min(klo, L.k_full);
@@ -64,45 +74,56 @@ __device__ __forceinline__ RowLayout row_layout(const ITile &t, int off, int n) 
     return L;
 }
 
-// Fixed-order sum over the streams of each atom: level 1 adds runs of C
-// consecutive streams, level 2 adds the runs.  sh holds 64*W doubles per
-// value; v[q] are this thread's partial sums.  Returns the totals to threads
-// il < ni (others get 0).
+// Double moved across lanes with a DPP control (all source lanes valid).
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 8 lanes of a group: pairs (quad_perm 1,0,3,2), quads
+// (quad_perm 2,3,0,1), then the two quads (row_half_mirror).  Every lane of
+// the group ends with the same value (commuted operands only).
+__device__ __forceinline__ double group8_sum(double x) {
+    x += dpp<0xB1>(x);
+    x += dpp<0x4E>(x);
+    x += dpp<0x141>(x);
+    return x;
+}
+
+// Totals of Q values per atom: group sums with DPP, then per atom over its G
+// groups in group order.  Returns the totals to threads t < ni (for atom t),
+// zeros elsewhere.  sh holds Q * 8 W doubles.
 template <int W, int Q>
 __device__ __forceinline__ void row_reduce(const RowLayout &L, double (&v)[Q], double *sh) {
-    constexpr int T = 64 * W;
+    constexpr int NG = 8 * W;
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) sh[q * T + tid] = L.active ? v[q] : 0.0;
-    __syncthreads();
-    // level 1: G1 runs of C streams per atom
-    int C = 1;
-    while (C * C < L.S) ++C;
-    const int G1 = (L.S + C - 1) / C;
-    double p[Q];
+    for (int q = 0; q < Q; ++q) v[q] = group8_sum(L.active ? v[q] : 0.0);
+    if ((tid & 7) == 0) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) p[q] = 0.0;
-    const bool lvl1 = tid < L.ni * G1;
-    if (lvl1) {
-        const int il = tid % L.ni, g = tid / L.ni;
-        const int s0 = g * C, s1 = min(L.S, s0 + C);
-        for (int s = s0; s < s1; ++s) {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) p[q] += sh[q * T + il + L.ni * s];
-        }
-    }
-    __syncthreads();
-    if (lvl1) {
-#pragma unroll
-        for (int q = 0; q < Q; ++q) sh[q * T + tid] = p[q];
+        for (int q = 0; q < Q; ++q) sh[q * NG + (tid >> 3)] = v[q];
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < Q; ++q) v[q] = 0.0;
     if (tid < L.ni) {
-        for (int g = 0; g < G1; ++g) {
+        int g = 0;
+        for (; g + 4 <= L.G; g += 4) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) v[q] += sh[q * T + tid + L.ni * g];
+            for (int q = 0; q < Q; ++q) {
+                const double a = sh[q * NG + tid + L.ni * g], b = sh[q * NG + tid + L.ni * (g + 1)];
+                const double c = sh[q * NG + tid + L.ni * (g + 2)], d = sh[q * NG + tid + L.ni * (g + 3)];
+                v[q] += a;
+                v[q] += b;
+                v[q] += c;
+                v[q] += d;
+            }
+        }
+        for (; g < L.G; ++g) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) v[q] += sh[q * NG + tid + L.ni * g];
         }
     }
 }
@@ -114,188 +135,396 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
+// The workgroup's tile: from the arguments for a single cluster with equal
+// runs (no table loads), else from the tables in launch order.
+struct RowTile {
+    int tix, i0, ni, off, n;
+};
+
+struct RowArgs {
+    const ITile *tiles;
+    const int32_t *order;
+    const ClusterDesc *cd;
+    int uni_off, uni_n, uni_ni;
+};
+
+__device__ __forceinline__ RowTile row_tile(const RowArgs &a) {
+    RowTile r;
+    if (a.uni_ni > 0) {
+        r.tix = blockIdx.x;
+        r.off = a.uni_off;
+        r.n = a.uni_n;
+        r.i0 = a.uni_off + r.tix * a.uni_ni;
+        r.ni = min(a.uni_ni, a.uni_n - r.tix * a.uni_ni);
+    } else {
+        r.tix = a.order[blockIdx.x];
+        const ITile t = a.tiles[r.tix];
+        const ClusterDesc d = a.cd[t.c];
+        r.i0 = t.i0;
+        r.ni = t.ni;
+        r.off = d.off;
+        r.n = d.n;
+    }
+    return r;
+}
+
+// LDS of a row workgroup: the staged partners (STAGE) followed by the
+// reduce area.
+template <int W, int Q, bool STAGE>
+constexpr size_t row_lds_bytes(int n) {
+    return (STAGE ? (size_t)n * sizeof(double4) : 0) + (size_t)Q * 8 * W * sizeof(double);
+}
+
+// The partner loop over rounds k in [ka, kb) of this thread's stream: plain
+// rounds in blocks of four through pointers stepped by 4 S, masked rounds
+// (self window, end of the cluster) one by one.  src points at the cluster's
+// first atom (LDS or global); pair(q, self) adds one partner.
+template <typename PAIR>
+__device__ __forceinline__ void row_loop(const RowLayout &L, const double4 *__restrict__ src, int n, int i_local,
+                                         PAIR &&pair, int ka, int kb) {
+    const int S = L.S;
+    int k = ka;
+    auto plain = [&](int k1) {
+        if (k >= k1) return;
+        const double4 *p0 = src + (L.s + (size_t)k * S);
+        if (k + 4 <= k1) {
+            const double4 *p1 = p0 + S, *p2 = p1 + S, *p3 = p2 + S;
+            const size_t S4 = 4 * (size_t)S;
+            for (; k + 4 <= k1; k += 4, p0 += S4, p1 += S4, p2 += S4, p3 += S4) {
+                const double4 a = *p0, b = *p1, c = *p2, e = *p3;
+                pair(a, false);
+                pair(b, false);
+                pair(c, false);
+                pair(e, false);
+            }
+        }
+        for (; k < k1; ++k, p0 += S) pair(*p0, false);
+    };
+    auto masked = [&](int k1) {
+        for (int j = L.s + k * S; k < k1; ++k, j += S) {
+            const bool valid = j < n;
+            const double4 a = src[valid ? j : 0];
+            pair(a, !valid || j == i_local);
+        }
+    };
+    plain(min(kb, L.k_mask0));
+    masked(min(kb, L.k_mask1));
+    plain(min(kb, L.k_full));
+    masked(min(kb, L.k_end));
+}
+
+// Staged sweeps copy the whole cluster into LDS before the pair loop.
+// Every thread issues the loads of four atoms before it stores any of them
+// (named registers: an array here would live in scratch), so four atoms per
+// thread cost one memory round trip.  All workgroups read the same atoms, so
+// the copy is bound by the L2-to-CU bandwidth (bytes per atom x workgroups).
+template <int W>
+__device__ __forceinline__ void stage_copy(double4 *lj, const double4 *__restrict__ g, int n) {
+    constexpr int T = 64 * W;
+    for (int a0 = threadIdx.x; a0 < n; a0 += 4 * T) {
+        const int a1 = a0 + T, a2 = a1 + T, a3 = a2 + T;
+        double4 t0 = g[a0], t1, t2, t3;
+        if (a1 < n) t1 = g[a1];
+        if (a2 < n) t2 = g[a2];
+        if (a3 < n) t3 = g[a3];
+        lj[a0] = t0;
+        if (a1 < n) lj[a1] = t1;
+        if (a2 < n) lj[a2] = t2;
+        if (a3 < n) lj[a3] = t3;
+    }
+    __syncthreads();
+}
+
+// Drift arguments of the density sweep (see RowDrift).
+struct RowDriftArgs {
+    int mode, local;
+    const double4 *v, *f;
+    ClusterState *st;
+    const double *tile_sums;
+    const ClusterDesc *cd;
+    double mass_u, dt, h;
+};
+
+// Drifted position r + dt (lambda v + h F), the same arithmetic as the drift
+// kernel (only x, y, z of r, v and F are read).
+struct DriftIn {
+    double4 r, v, f;
+};
+__device__ __forceinline__ double4 xyz(const double4 *__restrict__ p, int a) {
+    const double *q = reinterpret_cast<const double *>(p + a);
+    return make_double4(q[0], q[1], q[2], 0.0);
+}
+__device__ __forceinline__ DriftIn drift_load(const double4 *__restrict__ r, const double4 *__restrict__ v,
+                                              const double4 *__restrict__ f, int a) {
+    return DriftIn{xyz(r, a), xyz(v, a), xyz(f, a)};
+}
+__device__ __forceinline__ double drift1(double r, double v, double f, double lam, double dt, double h) {
+#pragma clang fp contract(off)
+    double u = lam * v;
+    u = u + h * f;
+    return r + dt * u;
+}
+__device__ __forceinline__ double4 drifted(const DriftIn &in, double lam, double dt, double h) {
+    return make_double4(drift1(in.r.x, in.v.x, in.f.x, lam, dt, h), drift1(in.r.y, in.v.y, in.f.y, lam, dt, h),
+                        drift1(in.r.z, in.v.z, in.f.z, lam, dt, h), 0.0);
+}
+
+// Force epilogue of a step whose drift ran inside the density sweep: the
+// velocity gets the thermostat factor and the first half-kick with the old
+// force (as in the drift kernel), then the second half-kick with the new one;
+// the drifted position r (x, y, z of the density output) is stored.
+__device__ __forceinline__ void force_atom_fused(int i, double fx, double fy, double fz, double eu, const double4 &r,
+                                                 const double4 &v_old, const double4 &f_old, const ForceOut &o,
+                                                 const PotConst &pc, double &epair, double &v2) {
+#pragma clang fp contract(off)
+    const double ei = pc.half_eps_an * eu;
+    const double lam = o.st->lambda;
+    const double4 fo = f_old;
+    double4 vi = v_old;
+    vi.x = lam * vi.x;
+    vi.y = lam * vi.y;
+    vi.z = lam * vi.z;
+    vi.x = vi.x + o.h * fo.x;
+    vi.y = vi.y + o.h * fo.y;
+    vi.z = vi.z + o.h * fo.z;
+    o.f[i] = make_double4(fx, fy, fz, ei);
+    vi.x = vi.x + o.h * fx;
+    vi.y = vi.y + o.h * fy;
+    vi.z = vi.z + o.h * fz;
+    o.v[i] = vi;
+    o.rp[i] = make_double4(r.x, r.y, r.z, 0.0);
+    epair += ei;
+    v2 += vi.x * vi.x + vi.y * vi.y + vi.z * vi.z;
+}
+
 // ---------------------------------------------------------------------------
 // Density sweep
 // ---------------------------------------------------------------------------
-template <int W, int PREC, bool GEN>
-__global__ __launch_bounds__(64 * W) void k_row_density(const ITile *__restrict__ tiles,
-                                                        const int32_t *__restrict__ order,
-                                                        const ClusterDesc *__restrict__ cd, DensityOut o,
-                                                        PotConst pc) {
-    __shared__ double sh[64 * W];
-    const int tix = order[blockIdx.x];
-    const ITile t = tiles[tix];
-    const ClusterDesc d = cd[t.c];
-    const RowLayout L = row_layout<W>(t, d.off, d.n);
-    const double4 qi = o.rp[L.i];
-    const double4 *__restrict__ rp = o.rp;
+template <int W, int PREC, bool GEN, bool STAGE>
+__global__ __launch_bounds__(64 * W) void k_row_density(RowArgs ra, DensityOut o, PotConst pc, RowDriftArgs da) {
+    extern __shared__ double4 lds_row[];
+    const RowTile rt = row_tile(ra);
+    const RowLayout L = row_layout<W>(rt.i0, rt.ni, rt.off, rt.n);
+    const int i_local = L.i - rt.off;
+    const int tid = threadIdx.x;
     double acc = 0.0;
-    const int S = L.S;
-    const int j0 = d.off + L.s;
-    int k = 0;
-    // partner rounds without masks; four pointers stepped by 4 S (one
-    // 64-bit add per load)
-    auto plain = [&](int k1) {
-        if (k >= k1) return;
-        const double4 *p0 = rp + (j0 + (size_t)k * S);
-        const double4 *p1 = p0 + S, *p2 = p1 + S, *p3 = p2 + S;
-        const size_t S4 = 4 * (size_t)S;
-        for (; k + 4 <= k1; k += 4, p0 += S4, p1 += S4, p2 += S4, p3 += S4) {
-            const double4 a = *p0, b = *p1, c = *p2, e = *p3;
+    double4 qi;
+    auto pair = [&](const double4 &a, bool self) {
+        if (self)
+            density_pair<PREC, GEN, true, false>(qi.x - a.x, qi.y - a.y, qi.z - a.z, true, acc, pc);
+        else
             density_pair<PREC, GEN, false, false>(qi.x - a.x, qi.y - a.y, qi.z - a.z, false, acc, pc);
-            density_pair<PREC, GEN, false, false>(qi.x - b.x, qi.y - b.y, qi.z - b.z, false, acc, pc);
-            density_pair<PREC, GEN, false, false>(qi.x - c.x, qi.y - c.y, qi.z - c.z, false, acc, pc);
-            density_pair<PREC, GEN, false, false>(qi.x - e.x, qi.y - e.y, qi.z - e.z, false, acc, pc);
-        }
-        for (; k < k1; ++k, p0 += S) {
-            const double4 a = *p0;
-            density_pair<PREC, GEN, false, false>(qi.x - a.x, qi.y - a.y, qi.z - a.z, false, acc, pc);
-        }
     };
-    auto masked = [&](int k1) {
-        const int end = d.off + d.n;
-        for (int j = j0 + k * S; k < k1; ++k, j += S) {
-            const bool valid = j < end;
-            const double4 a = rp[valid ? j : d.off];
-            density_pair<PREC, GEN, true, false>(qi.x - a.x, qi.y - a.y, qi.z - a.z, !valid || j == L.i, acc, pc);
+    const double4 *src = o.rp + rt.off;
+    double *sh = reinterpret_cast<double *>(lds_row);
+    if constexpr (STAGE) {
+        double4 *lj = lds_row;
+        sh += 4 * (size_t)rt.n;
+        if (da.mode == 0) {
+            qi = src[i_local];
+            stage_copy<W>(lj, src, rt.n);
+        } else {
+            // single cluster: drift while staging.  The loads of the own atom
+            // and of the first batch are issued before the thermostat factor
+            // is known; the factor's tile-sum loads overlap them.
+            const double4 *gv = da.v + rt.off, *gf = da.f + rt.off;
+            const DriftIn own = drift_load(src, gv, gf, i_local);
+            // the first four atoms of this thread (named registers, see stage_copy)
+            constexpr int T = 64 * W;
+            const int a0 = tid, a1 = a0 + T, a2 = a1 + T, a3 = a2 + T;
+            DriftIn t0, t1, t2, t3;
+            if (a0 < rt.n) t0 = drift_load(src, gv, gf, a0);
+            if (a1 < rt.n) t1 = drift_load(src, gv, gf, a1);
+            if (a2 < rt.n) t2 = drift_load(src, gv, gf, a2);
+            if (a3 < rt.n) t3 = drift_load(src, gv, gf, a3);
+            __shared__ double sh_tot[12];
+            double lam;
+            if (da.mode == 2) {
+                // finish the previous step's thermostat factor (finalize order)
+                const ClusterDesc d = da.cd[0];
+                double e0, e1, v2;
+                cluster_totals<true>(d, da.tile_sums, sh_tot, e0, e1, v2);
+                const KinT kt = kinetic_temperature(d, da.mass_u, v2);
+                double tt;
+                lam = thermostat_lambda(d, da.dt, kt.T, da.st->step + da.local, &tt);
+                if (blockIdx.x == 0 && tid == 0) da.st->lambda = lam;
+            } else {
+                lam = da.st->lambda;
+            }
+            qi = drifted(own, lam, da.dt, da.h);
+            if (a0 < rt.n) lj[a0] = drifted(t0, lam, da.dt, da.h);
+            if (a1 < rt.n) lj[a1] = drifted(t1, lam, da.dt, da.h);
+            if (a2 < rt.n) lj[a2] = drifted(t2, lam, da.dt, da.h);
+            if (a3 < rt.n) lj[a3] = drifted(t3, lam, da.dt, da.h);
+            for (int b0 = tid + 4 * T; b0 < rt.n; b0 += 4 * T) {
+                const int b1 = b0 + T, b2 = b1 + T, b3 = b2 + T;
+                const DriftIn u0 = drift_load(src, gv, gf, b0);
+                DriftIn u1, u2, u3;
+                if (b1 < rt.n) u1 = drift_load(src, gv, gf, b1);
+                if (b2 < rt.n) u2 = drift_load(src, gv, gf, b2);
+                if (b3 < rt.n) u3 = drift_load(src, gv, gf, b3);
+                lj[b0] = drifted(u0, lam, da.dt, da.h);
+                if (b1 < rt.n) lj[b1] = drifted(u1, lam, da.dt, da.h);
+                if (b2 < rt.n) lj[b2] = drifted(u2, lam, da.dt, da.h);
+                if (b3 < rt.n) lj[b3] = drifted(u3, lam, da.dt, da.h);
+            }
+            __syncthreads();
         }
-    };
-    plain(L.k_mask0);
-    masked(L.k_mask1);
-    plain(L.k_full);
-    masked(L.k_end);
-
+        row_loop(L, lj, rt.n, i_local, pair, 0, L.k_end);
+        src = lj;
+    } else {
+        qi = src[i_local];
+        row_loop(L, src, rt.n, i_local, pair, 0, L.k_end);
+    }
     double v[1] = {acc};
     row_reduce<W, 1>(L, v, sh);
     double emb = 0.0;
-    if (threadIdx.x < L.ni) emb = density_atom(t.i0 + threadIdx.x, v[0], o, pc);
-    if (threadIdx.x < 64) {
+    if (tid < L.ni) emb = density_atom_at(rt.i0 + tid, v[0], src[rt.i0 - rt.off + tid], o, pc);
+    if (tid < 64) {
         emb = wave_sum(emb);
-        if (threadIdx.x == 0) o.tile_sums[(size_t)tix * kTileSums + 0] = emb;
+        if (tid == 0) o.tile_sums[(size_t)rt.tix * kTileSums + 0] = emb;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Force sweep
 // ---------------------------------------------------------------------------
-template <int W, int PREC, bool GEN>
-__global__ __launch_bounds__(64 * W) void k_row_force(const ITile *__restrict__ tiles,
-                                                      const int32_t *__restrict__ order,
-                                                      const ClusterDesc *__restrict__ cd, const double4 *__restrict__ xp,
-                                                      ForceOut o, PotConst pc) {
-    __shared__ double sh[4 * 64 * W];
-    const int tix = order[blockIdx.x];
-    const ITile t = tiles[tix];
-    const ClusterDesc d = cd[t.c];
-    const RowLayout L = row_layout<W>(t, d.off, d.n);
-    const double4 qi = xp[L.i];
+template <int W, int PREC, bool GEN, bool STAGE>
+__global__ __launch_bounds__(64 * W) void k_row_force(RowArgs ra, const double4 *__restrict__ xp, ForceOut o,
+                                                      PotConst pc) {
+    extern __shared__ double4 lds_row[];
+    const RowTile rt = row_tile(ra);
+    const RowLayout L = row_layout<W>(rt.i0, rt.ni, rt.off, rt.n);
+    const int i_local = L.i - rt.off;
+    const int tid = threadIdx.x;
+    const double4 *src = xp + rt.off;
+    const double4 qi = src[i_local];
     const double ci = -qi.w;
     const float cif = (float)ci;
     const float Af = (float)pc.A;
     double fx = 0.0, fy = 0.0, fz = 0.0, eu = 0.0;
-    const int S = L.S;
-    const int j0 = d.off + L.s;
-    int k = 0;
-    auto plain = [&](int k1) {
-        if (k >= k1) return;
-        const double4 *p0 = xp + (j0 + (size_t)k * S);
-        const double4 *p1 = p0 + S, *p2 = p1 + S, *p3 = p2 + S;
-        const size_t S4 = 4 * (size_t)S;
-        for (; k + 4 <= k1; k += 4, p0 += S4, p1 += S4, p2 += S4, p3 += S4) {
-            const double4 a = *p0, b = *p1, c = *p2, e = *p3;
+    auto pair = [&](const double4 &a, bool self) {
+        if (self)
+            force_pair<PREC, GEN, true, false>(qi.x - a.x, qi.y - a.y, qi.z - a.z, true, ci, a.w, cif, (float)a.w,
+                                               fx, fy, fz, eu, pc, Af);
+        else
             force_pair<PREC, GEN, false, false>(qi.x - a.x, qi.y - a.y, qi.z - a.z, false, ci, a.w, cif, (float)a.w,
                                                 fx, fy, fz, eu, pc, Af);
-            force_pair<PREC, GEN, false, false>(qi.x - b.x, qi.y - b.y, qi.z - b.z, false, ci, b.w, cif, (float)b.w,
-                                                fx, fy, fz, eu, pc, Af);
-            force_pair<PREC, GEN, false, false>(qi.x - c.x, qi.y - c.y, qi.z - c.z, false, ci, c.w, cif, (float)c.w,
-                                                fx, fy, fz, eu, pc, Af);
-            force_pair<PREC, GEN, false, false>(qi.x - e.x, qi.y - e.y, qi.z - e.z, false, ci, e.w, cif, (float)e.w,
-                                                fx, fy, fz, eu, pc, Af);
-        }
-        for (; k < k1; ++k, p0 += S) {
-            const double4 a = *p0;
-            force_pair<PREC, GEN, false, false>(qi.x - a.x, qi.y - a.y, qi.z - a.z, false, ci, a.w, cif, (float)a.w,
-                                                fx, fy, fz, eu, pc, Af);
-        }
     };
-    auto masked = [&](int k1) {
-        const int end = d.off + d.n;
-        for (int j = j0 + k * S; k < k1; ++k, j += S) {
-            const bool valid = j < end;
-            const double4 a = xp[valid ? j : d.off];
-            force_pair<PREC, GEN, true, false>(qi.x - a.x, qi.y - a.y, qi.z - a.z, !valid || j == L.i, ci, a.w, cif,
-                                               (float)a.w, fx, fy, fz, eu, pc, Af);
-        }
-    };
-    plain(L.k_mask0);
-    masked(L.k_mask1);
-    plain(L.k_full);
-    masked(L.k_end);
-
+    // the epilogue's own-atom loads are issued now, off the critical path
+    double4 v_own = make_double4(0, 0, 0, 0), f_own = make_double4(0, 0, 0, 0);
+    if (tid < L.ni) {
+        v_own = o.v[rt.i0 + tid];
+        if (o.fused) f_own = o.f[rt.i0 + tid];
+    }
+    double *sh = reinterpret_cast<double *>(lds_row);
+    if constexpr (STAGE) {
+        double4 *lj = lds_row;
+        sh += 4 * (size_t)rt.n;
+        stage_copy<W>(lj, src, rt.n);
+        row_loop(L, lj, rt.n, i_local, pair, 0, L.k_end);
+        src = lj;
+    } else {
+        row_loop(L, src, rt.n, i_local, pair, 0, L.k_end);
+    }
     unscale_force<PREC, GEN>(fx, fy, fz, eu);
     double v[4] = {fx, fy, fz, eu};
     row_reduce<W, 4>(L, v, sh);
     double epair = 0.0, v2 = 0.0;
-    if (threadIdx.x < L.ni) force_atom(t.i0 + threadIdx.x, v[0], v[1], v[2], v[3], o, pc, epair, v2);
-    if (threadIdx.x < 64) {
+    if (tid < L.ni) {
+        const int i = rt.i0 + tid;
+        if (o.fused)
+            force_atom_fused(i, v[0], v[1], v[2], v[3], src[i - rt.off], v_own, f_own, o, pc, epair, v2);
+        else
+            force_atom_v(i, v[0], v[1], v[2], v[3], v_own, o, pc, epair, v2);
+    }
+    if (tid < 64) {
         epair = wave_sum(epair);
         v2 = wave_sum(v2);
-        if (threadIdx.x == 0) {
-            o.tile_sums[(size_t)tix * kTileSums + 1] = epair;
-            o.tile_sums[(size_t)tix * kTileSums + 2] = v2;
+        if (tid == 0) {
+            o.tile_sums[(size_t)rt.tix * kTileSums + 1] = epair;
+            o.tile_sums[(size_t)rt.tix * kTileSums + 2] = v2;
         }
     }
 }
 
-template <int W, int PREC, bool GEN>
-hipError_t row_launch(bool force, const RowLaunch &L, const SweepBuffers &B, const ForceOut &fo, const PotConst &pc,
-                      hipStream_t s) {
+// Allow the kernel the dynamic LDS it needs (above the 64 KiB default).
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+template <int W, int PREC, bool GEN, bool STAGE>
+hipError_t row_launch(bool force, const RowLaunch &L, const SweepBuffers &B, const ForceOut &fo,
+                      const RowDriftArgs &da, const PotConst &pc, hipStream_t s) {
+    const RowArgs ra{L.tiles, L.order, L.cd, L.uni_off, L.uni_n, L.uni_ni};
+    hipError_t e;
     if (force) {
-        hipLaunchKernelGGL((k_row_force<W, PREC, GEN>), dim3(L.ntiles), dim3(64 * W), 0, s, L.tiles, L.order, L.cd,
-                           (const double4 *)B.xp, fo, pc);
+        const size_t lds = row_lds_bytes<W, 4, STAGE>(L.nmax);
+        auto kern = k_row_force<W, PREC, GEN, STAGE>;
+        if ((e = allow_lds(kern, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(L.ntiles), dim3(64 * W), lds, s, ra, (const double4 *)B.xp, fo, pc);
     } else {
+        const size_t lds = row_lds_bytes<W, 1, STAGE>(L.nmax);
+        auto kern = k_row_density<W, PREC, GEN, STAGE>;
+        if ((e = allow_lds(kern, lds)) != hipSuccess) return e;
         const DensityOut dout{B.rp, B.xp, B.rho, B.tile_sums};
-        hipLaunchKernelGGL((k_row_density<W, PREC, GEN>), dim3(L.ntiles), dim3(64 * W), 0, s, L.tiles, L.order, L.cd,
-                           dout, pc);
+        hipLaunchKernelGGL(kern, dim3(L.ntiles), dim3(64 * W), lds, s, ra, dout, pc, da);
     }
     return hipGetLastError();
 }
 
+template <int W, bool STAGE>
+hipError_t row_dispatch_ws(bool force, const RowLaunch &L, const SweepBuffers &B, const ForceOut &fo,
+                           const RowDriftArgs &da, const PotConst &pc, int precision, hipStream_t s) {
+    if (pc.generic) {
+        return precision == SCMD_MIXED ? row_launch<W, SCMD_MIXED, true, STAGE>(force, L, B, fo, da, pc, s)
+                                       : row_launch<W, SCMD_FP64, true, STAGE>(force, L, B, fo, da, pc, s);
+    }
+    return precision == SCMD_MIXED ? row_launch<W, SCMD_MIXED, false, STAGE>(force, L, B, fo, da, pc, s)
+                                   : row_launch<W, SCMD_FP64, false, STAGE>(force, L, B, fo, da, pc, s);
+}
+
 template <int W>
 hipError_t row_dispatch_w(bool force, const RowLaunch &L, const SweepBuffers &B, const ForceOut &fo,
-                          const PotConst &pc, int precision, hipStream_t s) {
-    if (pc.generic) {
-        return precision == SCMD_MIXED ? row_launch<W, SCMD_MIXED, true>(force, L, B, fo, pc, s)
-                                       : row_launch<W, SCMD_FP64, true>(force, L, B, fo, pc, s);
-    }
-    return precision == SCMD_MIXED ? row_launch<W, SCMD_MIXED, false>(force, L, B, fo, pc, s)
-                                   : row_launch<W, SCMD_FP64, false>(force, L, B, fo, pc, s);
+                          const RowDriftArgs &da, const PotConst &pc, int precision, hipStream_t s) {
+    return L.nmax <= kRowStageMax ? row_dispatch_ws<W, true>(force, L, B, fo, da, pc, precision, s)
+                                  : row_dispatch_ws<W, false>(force, L, B, fo, da, pc, precision, s);
 }
 
 hipError_t row_dispatch(bool force, const RowLaunch &L, const SweepBuffers &B, const ForceOut &fo,
-                        const PotConst &pc, int precision, hipStream_t s) {
+                        const RowDriftArgs &da, const PotConst &pc, int precision, hipStream_t s) {
     if (L.ntiles <= 0) return hipSuccess;
+    // the drift and the fused epilogue need one staged cluster
+    const bool one_staged = L.uni_ni > 0 && L.nmax <= kRowStageMax;
+    if ((da.mode != 0 || fo.fused) && !one_staged) return hipErrorInvalidValue;
     (void)hipGetLastError();
     switch (L.waves) {
-        case 4: return row_dispatch_w<4>(force, L, B, fo, pc, precision, s);
-        case 8: return row_dispatch_w<8>(force, L, B, fo, pc, precision, s);
-        case 16: return row_dispatch_w<16>(force, L, B, fo, pc, precision, s);
+        case 4: return row_dispatch_w<4>(force, L, B, fo, da, pc, precision, s);
+        case 8: return row_dispatch_w<8>(force, L, B, fo, da, pc, precision, s);
+        case 16: return row_dispatch_w<16>(force, L, B, fo, da, pc, precision, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-hipError_t launch_row_density(const RowLaunch &L, const SweepBuffers &B, const PotConst &pc, int precision,
-                              hipStream_t s) {
+hipError_t launch_row_density(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, const RowDrift &dr,
+                              const PotConst &pc, int precision, hipStream_t s) {
     const ForceOut fo{};
-    return row_dispatch(false, L, B, fo, pc, precision, s);
+    const RowDriftArgs da{dr.mode, dr.local, B.v, B.f, a.st, B.tile_sums, a.cd, a.mass_u, a.dt, a.h};
+    return row_dispatch(false, L, B, fo, da, pc, precision, s);
 }
 
-hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, const PotConst &pc,
-                            int precision, hipStream_t s) {
-    const ForceOut fo{B.f, B.v, B.tile_sums, a.h, a.advance};
-    return row_dispatch(true, L, B, fo, pc, precision, s);
+hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, int fused,
+                            const PotConst &pc, int precision, hipStream_t s) {
+    // the fused epilogue stores the drifted positions (rp is the context's
+    // writable position array; the sweeps otherwise only read it)
+    const ForceOut fo{B.f, B.v, B.tile_sums, a.h, a.advance, fused, a.st, const_cast<double4 *>(B.rp)};
+    const RowDriftArgs da{};
+    return row_dispatch(true, L, B, fo, da, pc, precision, s);
 }
 
 }  // namespace scmd
