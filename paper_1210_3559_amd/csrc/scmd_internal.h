@@ -110,6 +110,7 @@ struct SweepBuffers {
     double *rho;
     double *part;       // partial sums, slot-major
     double *tile_sums;  // kTileSums doubles per tile
+    double2 *dpv;       // row sweeps of one cluster: drift inputs (p = r + dt h F, v), 3 pairs per atom
 };
 
 struct StepArgs {
@@ -187,6 +188,9 @@ struct RowDrift {
     int mode;   // 0: positions as they are; 1: drift with st->lambda; 2: new lambda, then drift
     int local;  // mode 2: steps completed in this run (ramp index st->step + local)
 };
+// The drifted position is evaluated as p + (dt lambda) v with p = r + (dt h) F:
+// mode 1 forms p from r and F, mode 2 reads p and v as stored by the previous
+// fused force epilogue (48 bytes per atom), with the same rounding.
 hipError_t launch_row_density(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, const RowDrift &dr,
                               const PotConst &pc, int precision, hipStream_t s);
 hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, int fused,

@@ -78,6 +78,7 @@ struct scmd_ctx {
 
     // device state
     DevBuf<double4> rp, v, f;
+    DevBuf<double2> dpv;  // drift inputs of the fused row path (3 per atom)
     DevBuf<double> rho;
     DevBuf<int32_t> atom_cluster;
     DevBuf<ClusterDesc> d_cdesc;
@@ -595,7 +596,7 @@ StepArgs step_args(scmd_ctx *c, int advance) {
 }
 
 SweepBuffers buffers(scmd_ctx *c) {
-    return SweepBuffers{c->rp.p, c->xp.p, c->f.p, c->v.p, c->rho.p, c->d_part.p, c->d_tile_sums.p};
+    return SweepBuffers{c->rp.p, c->xp.p, c->f.p, c->v.p, c->rho.p, c->d_part.p, c->d_tile_sums.p, c->dpv.p};
 }
 
 // One pair sweep (with its profiling events).  Row sweeps of one staged
@@ -812,6 +813,7 @@ void release_device(scmd_ctx *c) {
     c->v.release();
     c->f.release();
     c->rho.release();
+    c->dpv.release();
     c->atom_cluster.release();
     c->d_cdesc.release();
     c->d_state.release();
@@ -1003,6 +1005,7 @@ int scmd_init_clusters(scmd_ctx *ctx, int n_clusters, const int64_t *offsets, co
         HIP_TRY(ctx, ctx->v.ensure(na));
         HIP_TRY(ctx, ctx->f.ensure(na));
         HIP_TRY(ctx, ctx->rho.ensure(na));
+        HIP_TRY(ctx, ctx->dpv.ensure(3 * na));
         HIP_TRY(ctx, ctx->atom_cluster.ensure(na));
         HIP_TRY(ctx, ctx->d_state.ensure(n_clusters));
         HIP_TRY(ctx, ctx->d_cdesc.ensure(n_clusters));

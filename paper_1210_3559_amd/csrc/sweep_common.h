@@ -278,6 +278,8 @@ struct ForceOut {
     int fused;
     const ClusterState *st;
     double4 *rp;
+    double2 *dpv;  // drift inputs of the next step (p, v)
+    double dth;    // dt h
 };
 
 struct FinalizeArgs {

@@ -239,34 +239,39 @@ __device__ __forceinline__ void stage_copy(double4 *lj, const double4 *__restric
 struct RowDriftArgs {
     int mode, local;
     const double4 *v, *f;
+    const double2 *dpv;
     ClusterState *st;
     const double *tile_sums;
     const ClusterDesc *cd;
-    double mass_u, dt, h;
+    double mass_u, dt, h, dth;
 };
 
-// Drifted position r + dt (lambda v + h F), the same arithmetic as the drift
-// kernel (only x, y, z of r, v and F are read).
-struct DriftIn {
-    double4 r, v, f;
+// Drifted position p + (dt lambda) v with p = r + (dt h) F (RowDrift).
+// Mode 1 reads r, v, F (x, y, z) and forms p; mode 2 reads p, v from the
+// three pairs (px, py), (pz, vx), (vy, vz) stored per atom.
+struct PV {
+    double px, py, pz, vx, vy, vz;
 };
 __device__ __forceinline__ double4 xyz(const double4 *__restrict__ p, int a) {
     const double *q = reinterpret_cast<const double *>(p + a);
     return make_double4(q[0], q[1], q[2], 0.0);
 }
-__device__ __forceinline__ DriftIn drift_load(const double4 *__restrict__ r, const double4 *__restrict__ v,
-                                              const double4 *__restrict__ f, int a) {
-    return DriftIn{xyz(r, a), xyz(v, a), xyz(f, a)};
-}
-__device__ __forceinline__ double drift1(double r, double v, double f, double lam, double dt, double h) {
+__device__ __forceinline__ double pcomp(double r, double f, double dth) {
 #pragma clang fp contract(off)
-    double u = lam * v;
-    u = u + h * f;
-    return r + dt * u;
+    return r + dth * f;
 }
-__device__ __forceinline__ double4 drifted(const DriftIn &in, double lam, double dt, double h) {
-    return make_double4(drift1(in.r.x, in.v.x, in.f.x, lam, dt, h), drift1(in.r.y, in.v.y, in.f.y, lam, dt, h),
-                        drift1(in.r.z, in.v.z, in.f.z, lam, dt, h), 0.0);
+__device__ __forceinline__ PV pv_from_rvf(const double4 *__restrict__ r, const double4 *__restrict__ v,
+                                          const double4 *__restrict__ f, int a, double dth) {
+    const double4 ra = xyz(r, a), va = xyz(v, a), fa = xyz(f, a);
+    return PV{pcomp(ra.x, fa.x, dth), pcomp(ra.y, fa.y, dth), pcomp(ra.z, fa.z, dth), va.x, va.y, va.z};
+}
+__device__ __forceinline__ PV pv_load(const double2 *__restrict__ d, int a) {
+    const double2 q0 = d[3 * a], q1 = d[3 * a + 1], q2 = d[3 * a + 2];
+    return PV{q0.x, q0.y, q1.x, q1.y, q2.x, q2.y};
+}
+__device__ __forceinline__ double4 drifted(const PV &q, double dtl) {
+#pragma clang fp contract(off)
+    return make_double4(q.px + dtl * q.vx, q.py + dtl * q.vy, q.pz + dtl * q.vz, 0.0);
 }
 
 // Force epilogue of a step whose drift ran inside the density sweep: the
@@ -293,6 +298,11 @@ __device__ __forceinline__ void force_atom_fused(int i, double fx, double fy, do
     vi.z = vi.z + o.h * fz;
     o.v[i] = vi;
     o.rp[i] = make_double4(r.x, r.y, r.z, 0.0);
+    // drift inputs of the next step: p = r + (dt h) F, v
+    double2 *d = o.dpv + 3 * (size_t)i;
+    d[0] = make_double2(r.x + o.dth * fx, r.y + o.dth * fy);
+    d[1] = make_double2(r.z + o.dth * fz, vi.x);
+    d[2] = make_double2(vi.y, vi.z);
     epair += ei;
     v2 += vi.x * vi.x + vi.y * vi.y + vi.z * vi.z;
 }
@@ -327,16 +337,21 @@ __global__ __launch_bounds__(64 * W) void k_row_density(RowArgs ra, DensityOut o
             // single cluster: drift while staging.  The loads of the own atom
             // and of the first batch are issued before the thermostat factor
             // is known; the factor's tile-sum loads overlap them.
+            // the own atom and the first four atoms of this thread are loaded
+            // before the thermostat factor is known (named registers, see
+            // stage_copy); mode 2 reads the stored (p, v), mode 1 forms p
             const double4 *gv = da.v + rt.off, *gf = da.f + rt.off;
-            const DriftIn own = drift_load(src, gv, gf, i_local);
-            // the first four atoms of this thread (named registers, see stage_copy)
+            const double2 *gd = da.dpv + 3 * (size_t)rt.off;
+            const bool stored = da.mode == 2;
+            auto load = [&](int a) { return stored ? pv_load(gd, a) : pv_from_rvf(src, gv, gf, a, da.dth); };
+            const PV own = load(i_local);
             constexpr int T = 64 * W;
             const int a0 = tid, a1 = a0 + T, a2 = a1 + T, a3 = a2 + T;
-            DriftIn t0, t1, t2, t3;
-            if (a0 < rt.n) t0 = drift_load(src, gv, gf, a0);
-            if (a1 < rt.n) t1 = drift_load(src, gv, gf, a1);
-            if (a2 < rt.n) t2 = drift_load(src, gv, gf, a2);
-            if (a3 < rt.n) t3 = drift_load(src, gv, gf, a3);
+            PV t0, t1, t2, t3;
+            if (a0 < rt.n) t0 = load(a0);
+            if (a1 < rt.n) t1 = load(a1);
+            if (a2 < rt.n) t2 = load(a2);
+            if (a3 < rt.n) t3 = load(a3);
             __shared__ double sh_tot[12];
             double lam;
             if (da.mode == 2) {
@@ -351,22 +366,23 @@ __global__ __launch_bounds__(64 * W) void k_row_density(RowArgs ra, DensityOut o
             } else {
                 lam = da.st->lambda;
             }
-            qi = drifted(own, lam, da.dt, da.h);
-            if (a0 < rt.n) lj[a0] = drifted(t0, lam, da.dt, da.h);
-            if (a1 < rt.n) lj[a1] = drifted(t1, lam, da.dt, da.h);
-            if (a2 < rt.n) lj[a2] = drifted(t2, lam, da.dt, da.h);
-            if (a3 < rt.n) lj[a3] = drifted(t3, lam, da.dt, da.h);
+            const double dtl = da.dt * lam;
+            qi = drifted(own, dtl);
+            if (a0 < rt.n) lj[a0] = drifted(t0, dtl);
+            if (a1 < rt.n) lj[a1] = drifted(t1, dtl);
+            if (a2 < rt.n) lj[a2] = drifted(t2, dtl);
+            if (a3 < rt.n) lj[a3] = drifted(t3, dtl);
             for (int b0 = tid + 4 * T; b0 < rt.n; b0 += 4 * T) {
                 const int b1 = b0 + T, b2 = b1 + T, b3 = b2 + T;
-                const DriftIn u0 = drift_load(src, gv, gf, b0);
-                DriftIn u1, u2, u3;
-                if (b1 < rt.n) u1 = drift_load(src, gv, gf, b1);
-                if (b2 < rt.n) u2 = drift_load(src, gv, gf, b2);
-                if (b3 < rt.n) u3 = drift_load(src, gv, gf, b3);
-                lj[b0] = drifted(u0, lam, da.dt, da.h);
-                if (b1 < rt.n) lj[b1] = drifted(u1, lam, da.dt, da.h);
-                if (b2 < rt.n) lj[b2] = drifted(u2, lam, da.dt, da.h);
-                if (b3 < rt.n) lj[b3] = drifted(u3, lam, da.dt, da.h);
+                const PV u0 = load(b0);
+                PV u1, u2, u3;
+                if (b1 < rt.n) u1 = load(b1);
+                if (b2 < rt.n) u2 = load(b2);
+                if (b3 < rt.n) u3 = load(b3);
+                lj[b0] = drifted(u0, dtl);
+                if (b1 < rt.n) lj[b1] = drifted(u1, dtl);
+                if (b2 < rt.n) lj[b2] = drifted(u2, dtl);
+                if (b3 < rt.n) lj[b3] = drifted(u3, dtl);
             }
             __syncthreads();
         }
@@ -514,7 +530,7 @@ hipError_t row_dispatch(bool force, const RowLaunch &L, const SweepBuffers &B, c
 hipError_t launch_row_density(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, const RowDrift &dr,
                               const PotConst &pc, int precision, hipStream_t s) {
     const ForceOut fo{};
-    const RowDriftArgs da{dr.mode, dr.local, B.v, B.f, a.st, B.tile_sums, a.cd, a.mass_u, a.dt, a.h};
+    const RowDriftArgs da{dr.mode, dr.local, B.v, B.f, B.dpv, a.st, B.tile_sums, a.cd, a.mass_u, a.dt, a.h, a.dt * a.h};
     return row_dispatch(false, L, B, fo, da, pc, precision, s);
 }
 
@@ -522,7 +538,8 @@ hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const Ste
                             const PotConst &pc, int precision, hipStream_t s) {
     // the fused epilogue stores the drifted positions (rp is the context's
     // writable position array; the sweeps otherwise only read it)
-    const ForceOut fo{B.f, B.v, B.tile_sums, a.h, a.advance, fused, a.st, const_cast<double4 *>(B.rp)};
+    const ForceOut fo{B.f, B.v, B.tile_sums, a.h, a.advance, fused, a.st, const_cast<double4 *>(B.rp), B.dpv,
+                      a.dt * a.h};
     const RowDriftArgs da{};
     return row_dispatch(true, L, B, fo, da, pc, precision, s);
 }
