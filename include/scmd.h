@@ -213,6 +213,26 @@ int scmd_get_energy(scmd_ctx *ctx, int cluster, double out3[3]);
 /* Temperature (K) and degrees of freedom of one cluster's current state. */
 int scmd_get_temperature(scmd_ctx *ctx, int cluster, double *T_K, int64_t *ndof);
 
+/* Observables along a trajectory (the paper follows the energy per atom and
+ * the temperature of its runs, Sec. 3).  With every > 0, after each step k
+ * of the context step counter with k % every == 0, the state of every
+ * cluster is appended to a device ring buffer that keeps the last
+ * `capacity` samples; scmd_step splits its run at these steps (graph
+ * replays in between).  every = 0 stops sampling.  Any call clears the
+ * buffer.  SCMD_ESTATE before scmd_init_clusters; SCMD_EINVAL for
+ * every < 0, or capacity < 1 with every > 0; SCMD_ENOMEM if the buffer
+ * (capacity x n_clusters x 5 doubles) cannot be allocated.  scmd_init_clusters
+ * turns sampling off. */
+int scmd_set_sampling(scmd_ctx *ctx, int64_t every, int capacity);
+
+/* Samples of one cluster held in the buffer, oldest first: *n_out = number
+ * written (<= max_samples and <= capacity), out[5 s + 0..4] = { step,
+ * E_pot (eV), E_kin (eV), T (K), T_target (K, 0 without a thermostat) }.
+ * *recorded (may be NULL) = samples taken since the last
+ * scmd_set_sampling.  When more are held than max_samples, the newest
+ * max_samples are written. */
+int scmd_get_samples(scmd_ctx *ctx, int cluster, double *out, int max_samples, int *n_out, int64_t *recorded);
+
 /* Copy current state to host arrays of offsets[n_clusters] x 3 doubles
  * (density: offsets[n_clusters] doubles).  Velocities include any pending
  * thermostat factor.  Forces and density are those of the current positions

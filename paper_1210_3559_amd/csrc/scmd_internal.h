@@ -209,6 +209,9 @@ hipError_t launch_drift_fin(const StepArgs &a, const double *tile_sums, int loca
 hipError_t launch_drift(const int32_t *atom_cluster, const ClusterState *st, double4 *rp, double4 *v,
                         const double4 *f, int natoms, double dt, double h, hipStream_t s);
 hipError_t launch_aos_from4(const double4 *src, double *dst, int natoms, hipStream_t s);
+// Append the state of every cluster to ring slot `slot` (5 doubles per
+// cluster: step, E_pot, E_kin, T, T_target).
+hipError_t launch_sample(const ClusterState *st, int nclusters, double *ring, int slot, int64_t step, hipStream_t s);
 
 // Number of doubles per tile in tile_sums: [0] sum e_emb, [1] sum e_pair,
 // [2] sum v^2.

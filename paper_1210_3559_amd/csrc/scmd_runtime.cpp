@@ -79,6 +79,11 @@ struct scmd_ctx {
     // device state
     DevBuf<double4> rp, v, f;
     DevBuf<double2> dpv;  // drift inputs of the fused row path (3 per atom)
+    // sampled observables (ring buffer of sample_cap slots x nclusters x 5)
+    int64_t sample_every = 0;
+    int sample_cap = 0;
+    int64_t sample_total = 0;
+    DevBuf<double> d_samples;
     DevBuf<double> rho;
     DevBuf<int32_t> atom_cluster;
     DevBuf<ClusterDesc> d_cdesc;
@@ -760,6 +765,23 @@ int sync_and_check(scmd_ctx *c) {
     return SCMD_OK;
 }
 
+// nsteps steps as graph replays plus an eager remainder; every replay and
+// run ends with the per-cluster finalize, so the state is complete after it.
+int enqueue_chunk(scmd_ctx *c, int64_t nsteps) {
+    const bool use_graph = !(c->profiling && !c->graph_events_ok);
+    int64_t full = use_graph ? nsteps / kGraphSteps : 0;
+    int64_t rem = nsteps - full * kGraphSteps;
+    if (full > 0) {
+        int rc = ensure_graph(c);
+        if (rc != SCMD_OK) return rc;
+        for (int64_t r = 0; r < full; ++r) HIP_TRY(c, hipGraphLaunch(c->graph, c->stream));
+        c->graph_unread = c->profiling != 0;
+    }
+    if (rem > 0) HIP_TRY(c, enqueue_run(c, c->stream, false, rem));
+    c->step += nsteps;
+    return SCMD_OK;
+}
+
 int enqueue_steps(scmd_ctx *c, int64_t nsteps) {
     int rc = ensure_plan(c);
     if (rc != SCMD_OK) return rc;
@@ -767,17 +789,18 @@ int enqueue_steps(scmd_ctx *c, int64_t nsteps) {
         HIP_TRY(c, enqueue_forces(c, c->stream, false, 0));
         c->have_forces = true;
     }
-    const bool use_graph = !(c->profiling && !c->graph_events_ok);
-    int64_t full = use_graph ? nsteps / kGraphSteps : 0;
-    int64_t rem = nsteps - full * kGraphSteps;
-    if (full > 0) {
-        rc = ensure_graph(c);
+    while (nsteps > 0) {
+        int64_t chunk = nsteps;
+        if (c->sample_every > 0) chunk = std::min(chunk, c->sample_every - c->step % c->sample_every);
+        rc = enqueue_chunk(c, chunk);
         if (rc != SCMD_OK) return rc;
-        for (int64_t r = 0; r < full; ++r) HIP_TRY(c, hipGraphLaunch(c->graph, c->stream));
-        c->graph_unread = c->profiling != 0;
+        nsteps -= chunk;
+        if (c->sample_every > 0 && c->step % c->sample_every == 0) {
+            const int slot = (int)(c->sample_total % c->sample_cap);
+            HIP_TRY(c, launch_sample(c->d_state.p, c->nclusters, c->d_samples.p, slot, c->step, c->stream));
+            ++c->sample_total;
+        }
     }
-    if (rem > 0) HIP_TRY(c, enqueue_run(c, c->stream, false, rem));
-    c->step += nsteps;
     return SCMD_OK;
 }
 
@@ -814,6 +837,7 @@ void release_device(scmd_ctx *c) {
     c->f.release();
     c->rho.release();
     c->dpv.release();
+    c->d_samples.release();
     c->atom_cluster.release();
     c->d_cdesc.release();
     c->d_state.release();
@@ -983,6 +1007,9 @@ int scmd_init_clusters(scmd_ctx *ctx, int n_clusters, const int64_t *offsets, co
         ctx->plan_ok = false;
         ctx->have_forces = false;
         ctx->step = 0;
+        ctx->sample_every = 0;
+        ctx->sample_cap = 0;
+        ctx->sample_total = 0;
         ctx->nclusters = n_clusters;
         ctx->natoms = (int)natoms;
         ctx->mass = mass_u;
@@ -1206,6 +1233,59 @@ int scmd_get_energy(scmd_ctx *ctx, int cluster, double out3[3]) {
         out3[0] = ep;
         out3[1] = ek;
         out3[2] = ep + ek;
+        return SCMD_OK;
+    })
+}
+
+int scmd_set_sampling(scmd_ctx *ctx, int64_t every, int capacity) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
+    if (every < 0) return fail(ctx, SCMD_EINVAL, "every must be >= 0");
+    if (every > 0 && capacity < 1) return fail(ctx, SCMD_EINVAL, "capacity must be >= 1");
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        ctx->sample_every = 0;
+        ctx->sample_cap = 0;
+        ctx->sample_total = 0;
+        if (every > 0) {
+            const size_t need = (size_t)capacity * (size_t)ctx->nclusters * 5;
+            if (ctx->d_samples.ensure(need) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(ctx, SCMD_ENOMEM, "sample buffer allocation failed");
+            }
+            ctx->sample_every = every;
+            ctx->sample_cap = capacity;
+        }
+        return SCMD_OK;
+    })
+}
+
+int scmd_get_samples(scmd_ctx *ctx, int cluster, double *out, int max_samples, int *n_out, int64_t *recorded) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
+    if (cluster < 0 || cluster >= ctx->nclusters) return fail(ctx, SCMD_EINVAL, "cluster index out of range");
+    if (!n_out || max_samples < 0 || (!out && max_samples > 0))
+        return fail(ctx, SCMD_EINVAL, "need n_out, max_samples >= 0 and out");
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        int rc = sync_and_check(ctx);
+        if (rc != SCMD_OK) return rc;
+        const int64_t held = ctx->sample_cap > 0 ? std::min<int64_t>(ctx->sample_total, ctx->sample_cap) : 0;
+        const int64_t take = std::min<int64_t>(held, max_samples);
+        if (take > 0) {
+            std::vector<double> ring((size_t)ctx->sample_cap * ctx->nclusters * 5);
+            HIP_TRY(ctx, hipMemcpy(ring.data(), ctx->d_samples.p, ring.size() * sizeof(double), hipMemcpyDeviceToHost));
+            // the newest `take` samples, oldest first
+            for (int64_t k = 0; k < take; ++k) {
+                const int64_t idx = ctx->sample_total - take + k;  // sample number
+                const size_t slot = (size_t)(idx % ctx->sample_cap);
+                const double *src = ring.data() + (slot * ctx->nclusters + cluster) * 5;
+                for (int q = 0; q < 5; ++q) out[5 * k + q] = src[q];
+            }
+        }
+        *n_out = (int)take;
+        if (recorded) *recorded = ctx->sample_total;
         return SCMD_OK;
     })
 }

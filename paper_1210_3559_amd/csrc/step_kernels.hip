@@ -69,6 +69,19 @@ __global__ __launch_bounds__(256) void k_drift_fin(dev::FinalizeArgs fa, double4
     rp[i] = ri;
 }
 
+__global__ __launch_bounds__(256) void k_sample(const ClusterState *__restrict__ st, int nclusters,
+                                                double *__restrict__ ring, int slot, double step) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nclusters) return;
+    const ClusterState s = st[c];
+    double *o = ring + ((size_t)slot * nclusters + c) * 5;
+    o[0] = step;
+    o[1] = s.epot;
+    o[2] = s.ekin;
+    o[3] = s.temp;
+    o[4] = s.ttarget;
+}
+
 __global__ __launch_bounds__(256) void k_aos_from4(const double4 *__restrict__ src, double *__restrict__ dst,
                                                    int natoms) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -96,6 +109,14 @@ hipError_t launch_drift_fin(const StepArgs &a, const double *tile_sums, int loca
     const dev::FinalizeArgs fa{a.cd, a.st, tile_sums, a.flag, a.mass_u, a.dt, 1, local, 0};
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_drift_fin, dim3((natoms + 255) / 256), dim3(256), 0, s, fa, rp, v, f, natoms, a.dt, a.h);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(const ClusterState *st, int nclusters, double *ring, int slot, int64_t step, hipStream_t s) {
+    if (nclusters <= 0) return hipSuccess;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_sample, dim3((nclusters + 255) / 256), dim3(256), 0, s, st, nclusters, ring, slot,
+                       (double)step);
     return hipGetLastError();
 }
 

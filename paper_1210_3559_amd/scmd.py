@@ -45,7 +45,7 @@ EXPORTS = (
     "scmd_step", "scmd_step_async", "scmd_synchronize", "scmd_get_step", "scmd_get_energy",
     "scmd_get_temperature", "scmd_get_positions", "scmd_get_velocities", "scmd_get_forces", "scmd_get_density",
     "scmd_get_forces_device", "scmd_get_state", "scmd_set_state", "scmd_set_profiling", "scmd_get_kernel_time",
-    "scmd_last_error",
+    "scmd_set_sampling", "scmd_get_samples", "scmd_last_error",
 )
 
 
@@ -111,6 +111,8 @@ def load(path: str = LIB_PATH):
         "scmd_set_state": (i32, [vp, vp, ctypes.c_size_t]),
         "scmd_set_profiling": (i32, [vp, i32]),
         "scmd_get_kernel_time": (i32, [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
+        "scmd_set_sampling": (i32, [vp, i64, i32]),
+        "scmd_get_samples": (i32, [vp, i32, dp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
         "scmd_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -228,6 +230,21 @@ def scmd_get_temperature(ctx, cluster: int = 0):
     d = ctypes.c_int64()
     _check(ctx, load().scmd_get_temperature(ctx, int(cluster), ctypes.byref(t), ctypes.byref(d)))
     return t.value, d.value
+
+
+def scmd_set_sampling(ctx, every: int, capacity: int = 1024) -> None:
+    _check(ctx, load().scmd_set_sampling(ctx, int(every), int(capacity)))
+
+
+def scmd_get_samples(ctx, cluster: int = 0, max_samples: int = 1 << 20):
+    """(samples, recorded): samples is an (n, 5) array of step, E_pot, E_kin,
+    T, T_target, oldest first; recorded counts every sample taken."""
+    out = np.zeros((max(int(max_samples), 1), 5))
+    n = ctypes.c_int()
+    rec = ctypes.c_int64()
+    _check(ctx, load().scmd_get_samples(ctx, int(cluster), _ptr(out), int(max_samples), ctypes.byref(n),
+                                        ctypes.byref(rec)))
+    return out[: n.value].copy(), rec.value
 
 
 def _get3(fn, ctx, natoms):
@@ -372,3 +389,9 @@ class Simulation:
 
     def temperature(self, cluster: int = 0):
         return scmd_get_temperature(self.ctx, cluster)
+
+    def set_sampling(self, every: int, capacity: int = 1024):
+        scmd_set_sampling(self.ctx, every, capacity)
+
+    def samples(self, cluster: int = 0, max_samples: int = 1 << 20):
+        return scmd_get_samples(self.ctx, cluster, max_samples)

@@ -537,3 +537,92 @@ def test_row_trajectory_parity_and_determinism(waves):
     assert outs[0][2][0] == pytest.approx(log[39, 0], rel=1e-10)
     assert outs[0][2][1] == pytest.approx(log[39, 1], rel=1e-10)
     assert outs[0][3][0] == pytest.approx(log[39, 2], rel=1e-10)
+
+
+# --------------------------------------------------------------------------
+# Sampled observables (ring buffer filled while stepping)
+# --------------------------------------------------------------------------
+def _check_samples(smp, log, rtol=1e-10):
+    for row in smp:
+        k = int(row[0])
+        np.testing.assert_allclose(row[1:4], log[k - 1, :3], rtol=rtol)
+        assert row[4] == pytest.approx(log[k - 1, 3], rel=1e-12, abs=0.0)
+
+
+def test_sampling_matches_oracle_log_nve():
+    w = inputs.c1_icosahedron()
+    _, _, _, log = oracle.vv_run(w.pos, w.vel, 100, dt=w.dt, thermostat=w.thermostat[0], nthreads=NT)
+    print("[parity] sampling C1 every 10", flush=True)
+    with scmd.Simulation.from_workload(w) as sim:
+        sim.set_sampling(10, capacity=64)
+        sim.step(37)
+        sim.step(63)
+        smp, rec = sim.samples(0)
+    assert rec == 10 and len(smp) == 10
+    np.testing.assert_array_equal(smp[:, 0], np.arange(10, 101, 10))
+    _check_samples(smp, log)
+
+
+def test_sampling_berendsen_ramp_and_ring_wrap():
+    # uneven calls, an interval that is not a multiple of the graph length,
+    # and a buffer smaller than the number of samples
+    w = inputs.c2_cooling()
+    _, _, _, log = oracle.vv_run(w.pos, w.vel, 66, dt=w.dt, thermostat=w.thermostat[0], nthreads=NT)
+    print("[parity] sampling C2 every 11, capacity 3", flush=True)
+    with scmd.Simulation.from_workload(w) as sim:
+        sim.set_sampling(11, capacity=3)
+        for n in (5, 40, 21):
+            sim.step(n)
+        smp, rec = sim.samples(0)
+        two, _ = sim.samples(0, max_samples=2)
+    assert rec == 6 and len(smp) == 3
+    np.testing.assert_array_equal(smp[:, 0], [44, 55, 66])
+    np.testing.assert_array_equal(two, smp[1:])
+    _check_samples(smp, log)
+
+
+def test_sampling_batch_per_cluster():
+    sizes = [147, 0, 300, 64]
+    rng = np.random.default_rng(77)
+    parts = [_cluster(s, seed=60 + k, amp=0.05) for k, s in enumerate(sizes)]
+    vels = [inputs.maxwell_boltzmann(p, 1200.0, rng) if len(p) else np.zeros((0, 3)) for p in parts]
+    pos = np.concatenate(parts)
+    vel = np.concatenate(vels)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    print("[parity] sampling batch", flush=True)
+    with scmd.Simulation(offsets, pos, vel, dt=1.0) as sim:
+        sim.set_sampling(5, capacity=8)
+        sim.step(20)
+        got = [sim.samples(k) for k in range(len(sizes))]
+    for k, (p, v) in enumerate(zip(parts, vels)):
+        smp, rec = got[k]
+        assert rec == 4 and len(smp) == 4
+        np.testing.assert_array_equal(smp[:, 0], [5, 10, 15, 20])
+        if sizes[k] == 0:
+            assert np.all(smp[:, 1:] == 0.0)
+            continue
+        _, _, _, log = oracle.vv_run(p, v, 20, dt=1.0, nthreads=NT)
+        _check_samples(smp, log)
+
+
+def test_sampling_argument_errors():
+    ctx = scmd.scmd_create(0)
+    try:
+        with pytest.raises(scmd.ScmdError) as e:
+            scmd.scmd_set_sampling(ctx, 10, 4)
+        assert e.value.status == scmd.SCMD_ESTATE
+        scmd.scmd_init_clusters(ctx, np.array([0, 20]), _cluster(20), None, 58.6934)
+        with pytest.raises(scmd.ScmdError) as e:
+            scmd.scmd_set_sampling(ctx, -1, 4)
+        assert e.value.status == scmd.SCMD_EINVAL
+        with pytest.raises(scmd.ScmdError) as e:
+            scmd.scmd_set_sampling(ctx, 10, 0)
+        assert e.value.status == scmd.SCMD_EINVAL
+        scmd.scmd_set_sampling(ctx, 0, 0)
+        smp, rec = scmd.scmd_get_samples(ctx, 0)
+        assert len(smp) == 0 and rec == 0
+        with pytest.raises(scmd.ScmdError) as e:
+            scmd.scmd_get_samples(ctx, 1)
+        assert e.value.status == scmd.SCMD_EINVAL
+    finally:
+        scmd.scmd_destroy(ctx)
