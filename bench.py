@@ -13,7 +13,9 @@ FP64.  Prints one JSON line:
 
   value        whole-job atom-steps/s over exactly K timed steps
   roofline     the force sweep (dominant kernel): algorithmic FLOP per launch
-               (31 FLOP per unordered pair) / its device time per launch,
+               (30 FLOP per unordered pair: a step without the pair-energy
+               term, like all but the last step of each 32-step graph) / its
+               device time per launch,
                measured with HIP events inside the timed region, against the
                FP64 vector peak of MI355X (78.6 TFLOP/s)
   cpu_baseline the FP64 oracle on the host cores on a bounded sample of the
@@ -38,7 +40,11 @@ import numpy as np  # noqa: E402
 METRIC = "atom-steps/s and pair-interactions/s, Ni SC MD at 1 GPU: FP64 vs mixed vs batched"
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector (256 CU x 2.4 GHz x 128 FLOP/clk/CU)
 FLOP_DENSITY_PER_PAIR = 13.0  # algorithmic FLOP per unordered pair, density sweep
-FLOP_FORCE_PER_PAIR = 31.0  # algorithmic FLOP per unordered pair, force sweep
+# algorithmic FLOP per unordered pair of the timed force sweep: 31 with the
+# pair-energy term, 30 without it; the library accumulates the pair energy
+# only on the last step of each run (32-step graph replays, sampled steps),
+# and the sampled launch is a step without it
+FLOP_FORCE_PER_PAIR = 30.0
 
 
 def measured_traffic(workload: str):

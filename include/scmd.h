@@ -120,7 +120,7 @@ typedef struct {
     int pairs; /* 0 = library choice; 1 = one-sided sweeps (every atom owns its
                   sums, shapes above); 2 = symmetric sweeps (each unordered
                   pair evaluated once, j tiles rotated through the wavefront;
-                  ipt 2 or 4, waves_i and waves_j ignored; (n, m) = (9, 6) and
+                  ipt 2, 4 or 8, waves_i and waves_j ignored; (n, m) = (9, 6) and
                   all-pairs only); 3 = row sweeps (one workgroup of
                   64 * waves_j threads per run of at most 8 * waves_j atoms
                   against all of its partners, finished in the same launch;

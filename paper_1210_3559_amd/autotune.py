@@ -50,7 +50,7 @@ def tune(w, precision: str | None = None, budget_s: float = 0.25, shapes=SHAPES,
     table = []
     candidates = [(dict(ipt=ipt, waves_i=wi, waves_j=wj, pairs=1), targets) for ipt, wi, wj in shapes]
     if symmetric:
-        candidates += [(dict(ipt=ipt, pairs=2), targets) for ipt in (2, 4)]
+        candidates += [(dict(ipt=ipt, pairs=2), targets) for ipt in (2, 4, 8)]
     if row:
         candidates += [(dict(waves_j=wv, pairs=3), ROW_TARGETS) for wv in ROW_WAVES]
     for cand, tgts in candidates:

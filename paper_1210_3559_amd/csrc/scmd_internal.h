@@ -119,6 +119,7 @@ struct StepArgs {
     int *flag;          // non-finite flag
     double mass_u, dt, h;
     int advance;        // 1: kick + thermostat (second half of a step); 0: evaluate only
+    int energy;         // 1: accumulate the pair energy (symmetric and row force sweeps skip it otherwise)
 };
 
 // Pair sweeps.  Tiles whose partner range is one item are finished inside

@@ -455,8 +455,8 @@ int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
         c->sym = allowed && (c->tuning.pairs == 2 || (c->tuning.pairs == 0 && (batch || nmax > 4096)));
         if (c->sym) {
             int ipt = (batch || nmax > 32768) ? 4 : 2;
-            int target = batch ? 8192 : (nmax > 32768 ? 4096 : 2048);
-            if (c->tuning.ipt == 2 || c->tuning.ipt == 4) ipt = c->tuning.ipt;
+            int target = (batch || nmax > 32768) ? 8192 : 2048;
+            if (c->tuning.ipt == 2 || c->tuning.ipt == 4 || c->tuning.ipt == 8) ipt = c->tuning.ipt;
             if (c->tuning.target_items > 0) target = c->tuning.target_items;
             c->sym_ipt = ipt;
             return build_sym_plan(c, target);
@@ -596,19 +596,20 @@ hipError_t record(hipEvent_t ev, hipStream_t s, bool capturing) {
 
 double half_kick(const scmd_ctx *c) { return 0.5 * c->dt / (c->mass * kEvPerUA2Fs2); }
 
-StepArgs step_args(scmd_ctx *c, int advance) {
-    return StepArgs{c->d_cdesc.p, c->d_state.p, c->d_flag.p, c->mass, c->dt, half_kick(c), advance};
+StepArgs step_args(scmd_ctx *c, int advance, int energy = 1) {
+    return StepArgs{c->d_cdesc.p, c->d_state.p, c->d_flag.p, c->mass, c->dt, half_kick(c), advance, energy};
 }
 
 SweepBuffers buffers(scmd_ctx *c) {
     return SweepBuffers{c->rp.p, c->xp.p, c->f.p, c->v.p, c->rho.p, c->d_part.p, c->d_tile_sums.p, c->dpv.p};
 }
 
-// One pair sweep (with its profiling events).  Row sweeps of one staged
-// cluster take the drift (drift_mode, local: RowDrift) and the fused force
-// epilogue.
-hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int advance, int drift_mode = 0,
-                 int local = 0, int fused = 0) {
+// One pair sweep (with its profiling events).  energy = 0 lets the force
+// sweep skip the pair energy (steps whose energies nobody reads).  Row
+// sweeps of one staged cluster take the drift (drift_mode, local: RowDrift)
+// and the fused force epilogue.
+hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int advance, int energy = 1,
+                 int drift_mode = 0, int local = 0, int fused = 0) {
     int ev = -1;
     if (c->profiling && (!capturing || (c->graph_events_ok && c->capture_sample))) {
         ev = take_event(c, force ? SCMD_KERNEL_FORCE : SCMD_KERNEL_DENSITY);
@@ -618,7 +619,7 @@ hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int adv
         }
     }
     const SweepBuffers B = buffers(c);
-    const StepArgs A = step_args(c, advance);
+    const StepArgs A = step_args(c, advance, energy);
     hipError_t e;
     if (c->sym) {
         const SymLaunch L{c->d_sitems.p, c->d_sorder.p, c->d_stiles.p, c->sym_nitems, c->sym_ntiles, c->sym_ipt,
@@ -650,16 +651,16 @@ hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int adv
 // runs the thermostat (second half of a step).
 // Sweeps and tile finishes of one force evaluation (everything but the
 // per-cluster finalize).
-hipError_t enqueue_sweeps(scmd_ctx *c, hipStream_t s, bool capturing, int advance) {
+hipError_t enqueue_sweeps(scmd_ctx *c, hipStream_t s, bool capturing, int advance, int energy = 1) {
     hipError_t e;
     const SweepBuffers B = buffers(c);
-    const StepArgs A = step_args(c, advance);
+    const StepArgs A = step_args(c, advance, energy);
     if (c->sym) {
         const SymLaunch L{c->d_sitems.p, c->d_sorder.p, c->d_stiles.p, c->sym_nitems, c->sym_ntiles, c->sym_ipt,
                           c->d_ipart.p, c->d_jpart.p};
         if ((e = sweep(c, false, s, capturing, advance)) != hipSuccess) return e;
         if ((e = launch_sym_density(L, B, c->pc, c->precision, 1, s)) != hipSuccess) return e;
-        if ((e = sweep(c, true, s, capturing, advance)) != hipSuccess) return e;
+        if ((e = sweep(c, true, s, capturing, advance, energy)) != hipSuccess) return e;
         return launch_sym_force(L, B, A, c->pc, c->precision, 1, s);
     }
     if (c->neighbour == SCMD_CELLLIST) {
@@ -668,7 +669,7 @@ hipError_t enqueue_sweeps(scmd_ctx *c, hipStream_t s, bool capturing, int advanc
     if ((e = sweep(c, false, s, capturing, advance)) != hipSuccess) return e;
     if (c->has_split && (e = launch_density_reduce(c->d_tiles.p, c->ntiles, c->tile, B, c->pc, 2, s)) != hipSuccess)
         return e;
-    if ((e = sweep(c, true, s, capturing, advance)) != hipSuccess) return e;
+    if ((e = sweep(c, true, s, capturing, advance, energy)) != hipSuccess) return e;
     if (c->has_split && (e = launch_force_reduce(c->d_tiles.p, c->ntiles, c->tile, B, A, c->pc, 2, s)) != hipSuccess)
         return e;
     return hipSuccess;
@@ -682,8 +683,10 @@ hipError_t enqueue_forces(scmd_ctx *c, hipStream_t s, bool capturing, int advanc
     return launch_finalize(step_args(c, advance), c->d_tile_sums.p, c->nclusters, advance, s);
 }
 
-// A run of nsteps velocity-Verlet steps; the last step of a captured run
-// carries the sampled profiling events.  A single cluster finishes each step
+// A run of nsteps velocity-Verlet steps.  Only the last step of a run
+// accumulates the pair energy: the state is read (getters, samples) only
+// after a run.  The step before it carries the sampled profiling events of
+// a captured run (a step without the energy term, like all but one).  A single cluster finishes each step
 // inside the next step's drift (k_drift_fin) and the run's last step with the
 // per-cluster finalize, which also stores the step counter; a batch runs the
 // finalize after every step.
@@ -695,9 +698,11 @@ hipError_t enqueue_run(scmd_ctx *c, hipStream_t s, bool capturing, int64_t nstep
         // (after finishing the previous step's thermostat factor), the force
         // sweep's epilogue kicks and stores the positions
         for (int64_t k = 0; k < nsteps; ++k) {
-            if (capturing) c->capture_sample = (k == nsteps - 1);
-            if ((e = sweep(c, false, s, capturing, 1, k == 0 ? 1 : 2, (int)k)) != hipSuccess) return e;
-            if ((e = sweep(c, true, s, capturing, 1, 0, 0, 1)) != hipSuccess) return e;
+            // the sampled step is the last one without the pair energy
+            if (capturing) c->capture_sample = (k == std::max<int64_t>(0, nsteps - 2));
+            const int en = k == nsteps - 1;
+            if ((e = sweep(c, false, s, capturing, 1, 1, k == 0 ? 1 : 2, (int)k)) != hipSuccess) return e;
+            if ((e = sweep(c, true, s, capturing, 1, en, 0, 0, 1)) != hipSuccess) return e;
         }
         c->capture_sample = false;
         if (nsteps > 0) return launch_finalize(A, c->d_tile_sums.p, c->nclusters, (int)nsteps, s);
@@ -711,8 +716,8 @@ hipError_t enqueue_run(scmd_ctx *c, hipStream_t s, bool capturing, int64_t nstep
             e = launch_drift(c->atom_cluster.p, c->d_state.p, c->rp.p, c->v.p, c->f.p, c->natoms, c->dt,
                              half_kick(c), s);
         if (e != hipSuccess) return e;
-        if (capturing) c->capture_sample = (k == nsteps - 1);
-        e = enqueue_sweeps(c, s, capturing, 1);
+        if (capturing) c->capture_sample = (k == std::max<int64_t>(0, nsteps - 2));
+        e = enqueue_sweeps(c, s, capturing, 1, k == nsteps - 1);
         if (e != hipSuccess) return e;
         if (!fuse && (e = launch_finalize(A, c->d_tile_sums.p, c->nclusters, 1, s)) != hipSuccess) return e;
     }
@@ -1142,8 +1147,8 @@ int scmd_set_tuning(scmd_ctx *ctx, const scmd_tuning *t) {
     scmd_tuning z{};
     if (t) {
         if (t->pairs == 2) {
-            if (t->ipt != 0 && t->ipt != 2 && t->ipt != 4)
-                return fail(ctx, SCMD_EINVAL, "symmetric sweeps take ipt 2 or 4");
+            if (t->ipt != 0 && t->ipt != 2 && t->ipt != 4 && t->ipt != 8)
+                return fail(ctx, SCMD_EINVAL, "symmetric sweeps take ipt 2, 4 or 8");
         } else if (t->pairs == 3) {
             if (t->waves_j != 0 && t->waves_j != 4 && t->waves_j != 8 && t->waves_j != 16)
                 return fail(ctx, SCMD_EINVAL, "row sweeps take waves_j 4, 8 or 16");

@@ -129,7 +129,7 @@ __device__ __forceinline__ double rsq2_nr(double x) {
     return y * __builtin_fma(-x, y * y, 3.0);
 }
 
-template <int PREC, bool GEN, bool MASK, bool CUT>
+template <int PREC, bool GEN, bool MASK, bool CUT, bool EN = true>
 __device__ __forceinline__ void force_pair(double dx, double dy, double dz, bool self, double ci, double pj,
                                            float cif, float pjf, double &fx, double &fy, double &fz, double &eu,
                                            const PotConst &pc, float Af) {
@@ -148,7 +148,7 @@ __device__ __forceinline__ void force_pair(double dx, double dy, double dz, bool
             const double w8 = w4 * w4;
             const double q = __builtin_fma(pc.A8, w3, ci) - pj;
             f = w8 * q;   // 2^8 x the force coefficient
-            un = w8 * w;  // 2^9 u^n
+            if constexpr (EN) un = w8 * w;  // 2^9 u^n
         } else {
             double u = rsq_nr(r2);
             double um2 = powi(u, pc.m + 2);
@@ -160,7 +160,8 @@ __device__ __forceinline__ void force_pair(double dx, double dy, double dz, bool
         fx = __builtin_fma(f, dx, fx);
         fy = __builtin_fma(f, dy, fy);
         fz = __builtin_fma(f, dz, fz);
-        if constexpr (CUT) {
+        if constexpr (!EN) {
+        } else if constexpr (CUT) {
             eu += off ? 0.0 : un - (GEN ? pc.inv_rc_n : pc.inv_rc_n512);
         } else {
             eu += un;
@@ -181,7 +182,7 @@ __device__ __forceinline__ void force_pair(double dx, double dy, double dz, bool
             float u8 = u4 * u4;
             float q = __builtin_fmaf(Af, u3, cif) - pjf;
             f = u8 * q;
-            un = u8 * u;
+            if constexpr (EN) un = u8 * u;
         } else {
             float um2 = powi(u, pc.m + 2);
             float und = powi(u, pc.n - pc.m);
@@ -193,7 +194,8 @@ __device__ __forceinline__ void force_pair(double dx, double dy, double dz, bool
         fx = __builtin_fma(fd, dx, fx);
         fy = __builtin_fma(fd, dy, fy);
         fz = __builtin_fma(fd, dz, fz);
-        if constexpr (CUT) {
+        if constexpr (!EN) {
+        } else if constexpr (CUT) {
             eu += off ? 0.0 : (double)un - pc.inv_rc_n;
         } else {
             eu += (double)un;

@@ -405,7 +405,8 @@ __global__ __launch_bounds__(64 * W) void k_row_density(RowArgs ra, DensityOut o
 // ---------------------------------------------------------------------------
 // Force sweep
 // ---------------------------------------------------------------------------
-template <int W, int PREC, bool GEN, bool STAGE>
+// EN: accumulate the pair energy (otherwise the energy sums are zero).
+template <int W, int PREC, bool GEN, bool STAGE, bool EN>
 __global__ __launch_bounds__(64 * W) void k_row_force(RowArgs ra, const double4 *__restrict__ xp, ForceOut o,
                                                       PotConst pc) {
     extern __shared__ double4 lds_row[];
@@ -421,11 +422,11 @@ __global__ __launch_bounds__(64 * W) void k_row_force(RowArgs ra, const double4 
     double fx = 0.0, fy = 0.0, fz = 0.0, eu = 0.0;
     auto pair = [&](const double4 &a, bool self) {
         if (self)
-            force_pair<PREC, GEN, true, false>(qi.x - a.x, qi.y - a.y, qi.z - a.z, true, ci, a.w, cif, (float)a.w,
-                                               fx, fy, fz, eu, pc, Af);
+            force_pair<PREC, GEN, true, false, EN>(qi.x - a.x, qi.y - a.y, qi.z - a.z, true, ci, a.w, cif,
+                                                   (float)a.w, fx, fy, fz, eu, pc, Af);
         else
-            force_pair<PREC, GEN, false, false>(qi.x - a.x, qi.y - a.y, qi.z - a.z, false, ci, a.w, cif, (float)a.w,
-                                                fx, fy, fz, eu, pc, Af);
+            force_pair<PREC, GEN, false, false, EN>(qi.x - a.x, qi.y - a.y, qi.z - a.z, false, ci, a.w, cif,
+                                                    (float)a.w, fx, fy, fz, eu, pc, Af);
     };
     // the epilogue's own-atom loads are issued now, off the critical path
     double4 v_own = make_double4(0, 0, 0, 0), f_own = make_double4(0, 0, 0, 0);
@@ -444,6 +445,7 @@ __global__ __launch_bounds__(64 * W) void k_row_force(RowArgs ra, const double4 
         row_loop(L, src, rt.n, i_local, pair, 0, L.k_end);
     }
     unscale_force<PREC, GEN>(fx, fy, fz, eu);
+    if constexpr (!EN) eu = 0.0;
     double v[4] = {fx, fy, fz, eu};
     row_reduce<W, 4>(L, v, sh);
     double epair = 0.0, v2 = 0.0;
@@ -473,13 +475,14 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 }
 
 template <int W, int PREC, bool GEN, bool STAGE>
-hipError_t row_launch(bool force, const RowLaunch &L, const SweepBuffers &B, const ForceOut &fo,
+hipError_t row_launch(bool force, bool energy, const RowLaunch &L, const SweepBuffers &B, const ForceOut &fo,
                       const RowDriftArgs &da, const PotConst &pc, hipStream_t s) {
     const RowArgs ra{L.tiles, L.order, L.cd, L.uni_off, L.uni_n, L.uni_ni};
     hipError_t e;
     if (force) {
         const size_t lds = row_lds_bytes<W, 4, STAGE>(L.nmax);
-        auto kern = k_row_force<W, PREC, GEN, STAGE>;
+        // the generic-exponent kernels always accumulate the energy
+        auto kern = (energy || GEN) ? k_row_force<W, PREC, GEN, STAGE, true> : k_row_force<W, PREC, GEN, STAGE, GEN>;
         if ((e = allow_lds(kern, lds)) != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3(L.ntiles), dim3(64 * W), lds, s, ra, (const double4 *)B.xp, fo, pc);
     } else {
@@ -493,24 +496,24 @@ hipError_t row_launch(bool force, const RowLaunch &L, const SweepBuffers &B, con
 }
 
 template <int W, bool STAGE>
-hipError_t row_dispatch_ws(bool force, const RowLaunch &L, const SweepBuffers &B, const ForceOut &fo,
+hipError_t row_dispatch_ws(bool force, bool energy, const RowLaunch &L, const SweepBuffers &B, const ForceOut &fo,
                            const RowDriftArgs &da, const PotConst &pc, int precision, hipStream_t s) {
     if (pc.generic) {
-        return precision == SCMD_MIXED ? row_launch<W, SCMD_MIXED, true, STAGE>(force, L, B, fo, da, pc, s)
-                                       : row_launch<W, SCMD_FP64, true, STAGE>(force, L, B, fo, da, pc, s);
+        return precision == SCMD_MIXED ? row_launch<W, SCMD_MIXED, true, STAGE>(force, energy, L, B, fo, da, pc, s)
+                                       : row_launch<W, SCMD_FP64, true, STAGE>(force, energy, L, B, fo, da, pc, s);
     }
-    return precision == SCMD_MIXED ? row_launch<W, SCMD_MIXED, false, STAGE>(force, L, B, fo, da, pc, s)
-                                   : row_launch<W, SCMD_FP64, false, STAGE>(force, L, B, fo, da, pc, s);
+    return precision == SCMD_MIXED ? row_launch<W, SCMD_MIXED, false, STAGE>(force, energy, L, B, fo, da, pc, s)
+                                   : row_launch<W, SCMD_FP64, false, STAGE>(force, energy, L, B, fo, da, pc, s);
 }
 
 template <int W>
-hipError_t row_dispatch_w(bool force, const RowLaunch &L, const SweepBuffers &B, const ForceOut &fo,
+hipError_t row_dispatch_w(bool force, bool energy, const RowLaunch &L, const SweepBuffers &B, const ForceOut &fo,
                           const RowDriftArgs &da, const PotConst &pc, int precision, hipStream_t s) {
-    return L.nmax <= kRowStageMax ? row_dispatch_ws<W, true>(force, L, B, fo, da, pc, precision, s)
-                                  : row_dispatch_ws<W, false>(force, L, B, fo, da, pc, precision, s);
+    return L.nmax <= kRowStageMax ? row_dispatch_ws<W, true>(force, energy, L, B, fo, da, pc, precision, s)
+                                  : row_dispatch_ws<W, false>(force, energy, L, B, fo, da, pc, precision, s);
 }
 
-hipError_t row_dispatch(bool force, const RowLaunch &L, const SweepBuffers &B, const ForceOut &fo,
+hipError_t row_dispatch(bool force, bool energy, const RowLaunch &L, const SweepBuffers &B, const ForceOut &fo,
                         const RowDriftArgs &da, const PotConst &pc, int precision, hipStream_t s) {
     if (L.ntiles <= 0) return hipSuccess;
     // the drift and the fused epilogue need one staged cluster
@@ -518,9 +521,9 @@ hipError_t row_dispatch(bool force, const RowLaunch &L, const SweepBuffers &B, c
     if ((da.mode != 0 || fo.fused) && !one_staged) return hipErrorInvalidValue;
     (void)hipGetLastError();
     switch (L.waves) {
-        case 4: return row_dispatch_w<4>(force, L, B, fo, da, pc, precision, s);
-        case 8: return row_dispatch_w<8>(force, L, B, fo, da, pc, precision, s);
-        case 16: return row_dispatch_w<16>(force, L, B, fo, da, pc, precision, s);
+        case 4: return row_dispatch_w<4>(force, energy, L, B, fo, da, pc, precision, s);
+        case 8: return row_dispatch_w<8>(force, energy, L, B, fo, da, pc, precision, s);
+        case 16: return row_dispatch_w<16>(force, energy, L, B, fo, da, pc, precision, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -531,7 +534,7 @@ hipError_t launch_row_density(const RowLaunch &L, const SweepBuffers &B, const S
                               const PotConst &pc, int precision, hipStream_t s) {
     const ForceOut fo{};
     const RowDriftArgs da{dr.mode, dr.local, B.v, B.f, B.dpv, a.st, B.tile_sums, a.cd, a.mass_u, a.dt, a.h, a.dt * a.h};
-    return row_dispatch(false, L, B, fo, da, pc, precision, s);
+    return row_dispatch(false, true, L, B, fo, da, pc, precision, s);
 }
 
 hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, int fused,
@@ -541,7 +544,7 @@ hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const Ste
     const ForceOut fo{B.f, B.v, B.tile_sums, a.h, a.advance, fused, a.st, const_cast<double4 *>(B.rp), B.dpv,
                       a.dt * a.h};
     const RowDriftArgs da{};
-    return row_dispatch(true, L, B, fo, da, pc, precision, s);
+    return row_dispatch(true, a.energy != 0, L, B, fo, da, pc, precision, s);
 }
 
 }  // namespace scmd

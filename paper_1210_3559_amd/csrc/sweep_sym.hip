@@ -67,7 +67,7 @@ __device__ __forceinline__ void load_group(const SymItem &it, const SymTile *__r
 // ---------------------------------------------------------------------------
 // Force sweep
 // ---------------------------------------------------------------------------
-template <int PREC>
+template <int PREC, bool EN>
 __device__ __forceinline__ void sym_force_pair(double dx, double dy, double dz, double ci, double pj, float cif,
                                                float pjf, double &fx, double &fy, double &fz, double &eu,
                                                double &gx, double &gy, double &gz, const PotConst &pc, float Af) {
@@ -82,7 +82,7 @@ __device__ __forceinline__ void sym_force_pair(double dx, double dy, double dz, 
         const double w8 = w4 * w4;
         const double q = __builtin_fma(pc.A8, w3, ci) - pj;
         f = w8 * q;
-        un = w8 * w;
+        if constexpr (EN) un = w8 * w;
     } else {
         const double r2d = __builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz));
         const float u = __builtin_amdgcn_rsqf((float)r2d);
@@ -92,7 +92,7 @@ __device__ __forceinline__ void sym_force_pair(double dx, double dy, double dz, 
         const float u8 = u4 * u4;
         const float q = __builtin_fmaf(Af, u3, cif) - pjf;
         f = (double)(u8 * q);
-        un = (double)(u8 * u);
+        if constexpr (EN) un = (double)(u8 * u);
     }
     fx = __builtin_fma(f, dx, fx);
     fy = __builtin_fma(f, dy, fy);
@@ -100,10 +100,12 @@ __device__ __forceinline__ void sym_force_pair(double dx, double dy, double dz, 
     gx = __builtin_fma(-f, dx, gx);
     gy = __builtin_fma(-f, dy, gy);
     gz = __builtin_fma(-f, dz, gz);
-    eu += un;
+    if constexpr (EN) eu += un;
 }
 
-template <int IPT, int PREC>
+// EN: accumulate the pair energy (u^n); without it the energy partials are
+// written as zero (steps whose energies nobody reads).
+template <int IPT, int PREC, bool EN>
 __global__ __launch_bounds__(64) void k_sym_force(const SymItem *__restrict__ items, const int32_t *__restrict__ order,
                                                   const SymTile *__restrict__ tiles, const double4 *__restrict__ xp,
                                                   double *__restrict__ ipart, double *__restrict__ jpart,
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(64) void k_sym_force(const SymItem *__restrict__ it
                 const float pjf = (float)pj;
 #pragma unroll
                 for (int p = 0; p < IPT; ++p) {
-                    sym_force_pair<PREC>(G.x[p] - xj, G.y[p] - yj, G.z[p] - zj, G.c[p], pj, cif[p], pjf, fx[p], fy[p],
+                    sym_force_pair<PREC, EN>(G.x[p] - xj, G.y[p] - yj, G.z[p] - zj, G.c[p], pj, cif[p], pjf, fx[p], fy[p],
                                          fz[p], eu[p], gx, gy, gz, pc, Af);
                 }
                 xj = ror1(xj);
@@ -173,7 +175,10 @@ __global__ __launch_bounds__(64) void k_sym_force(const SymItem *__restrict__ it
         for (int p = 0; p < IPT; ++p) eu[p] *= 2.0;  // each unordered pair once
     }
 #pragma unroll
-    for (int p = 0; p < IPT; ++p) unscale_force<PREC, false>(fx[p], fy[p], fz[p], eu[p]);
+    for (int p = 0; p < IPT; ++p) {
+        unscale_force<PREC, false>(fx[p], fy[p], fz[p], eu[p]);
+        if constexpr (!EN) eu[p] = 0.0;
+    }
     double *out = ipart + (size_t)it.slot * 4 * 64 * IPT;
 #pragma unroll
     for (int p = 0; p < IPT; ++p) {
@@ -330,13 +335,16 @@ __global__ __launch_bounds__(kSymRed) void k_sym_force_reduce(const SymTile *__r
 }
 
 template <int IPT, int PREC>
-hipError_t launch_ipt(bool force, int stage, const SymLaunch &L, const SweepBuffers &B, const ForceOut &fo,
-                      const PotConst &pc, hipStream_t s) {
+hipError_t launch_ipt(bool force, int stage, bool energy, const SymLaunch &L, const SweepBuffers &B,
+                      const ForceOut &fo, const PotConst &pc, hipStream_t s) {
     (void)hipGetLastError();
     if (stage == 0 && L.nitems > 0) {
-        if (force)
-            hipLaunchKernelGGL((k_sym_force<IPT, PREC>), dim3(L.nitems), dim3(64), 0, s, L.items, L.order, L.tiles,
-                               B.xp, L.ipart, L.jpart, pc);
+        if (force && energy)
+            hipLaunchKernelGGL((k_sym_force<IPT, PREC, true>), dim3(L.nitems), dim3(64), 0, s, L.items, L.order,
+                               L.tiles, B.xp, L.ipart, L.jpart, pc);
+        else if (force)
+            hipLaunchKernelGGL((k_sym_force<IPT, PREC, false>), dim3(L.nitems), dim3(64), 0, s, L.items, L.order,
+                               L.tiles, B.xp, L.ipart, L.jpart, pc);
         else
             hipLaunchKernelGGL((k_sym_density<IPT, PREC>), dim3(L.nitems), dim3(64), 0, s, L.items, L.order, L.tiles,
                                B.rp, L.ipart, L.jpart, pc);
@@ -355,11 +363,12 @@ hipError_t launch_ipt(bool force, int stage, const SymLaunch &L, const SweepBuff
 }
 
 template <int PREC>
-hipError_t dispatch_ipt(bool force, int stage, const SymLaunch &L, const SweepBuffers &B, const ForceOut &fo,
-                        const PotConst &pc, hipStream_t s) {
+hipError_t dispatch_ipt(bool force, int stage, bool energy, const SymLaunch &L, const SweepBuffers &B,
+                        const ForceOut &fo, const PotConst &pc, hipStream_t s) {
     switch (L.ipt) {
-        case 2: return launch_ipt<2, PREC>(force, stage, L, B, fo, pc, s);
-        case 4: return launch_ipt<4, PREC>(force, stage, L, B, fo, pc, s);
+        case 2: return launch_ipt<2, PREC>(force, stage, energy, L, B, fo, pc, s);
+        case 4: return launch_ipt<4, PREC>(force, stage, energy, L, B, fo, pc, s);
+        case 8: return launch_ipt<8, PREC>(force, stage, energy, L, B, fo, pc, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -369,16 +378,17 @@ hipError_t dispatch_ipt(bool force, int stage, const SymLaunch &L, const SweepBu
 hipError_t launch_sym_density(const SymLaunch &L, const SweepBuffers &B, const PotConst &pc, int precision,
                               int stage, hipStream_t s) {
     if (pc.generic || pc.cut) return hipErrorInvalidValue;
-    return precision == SCMD_FP64 ? dispatch_ipt<SCMD_FP64>(false, stage, L, B, ForceOut{}, pc, s)
-                                  : dispatch_ipt<SCMD_MIXED>(false, stage, L, B, ForceOut{}, pc, s);
+    return precision == SCMD_FP64 ? dispatch_ipt<SCMD_FP64>(false, stage, true, L, B, ForceOut{}, pc, s)
+                                  : dispatch_ipt<SCMD_MIXED>(false, stage, true, L, B, ForceOut{}, pc, s);
 }
 
 hipError_t launch_sym_force(const SymLaunch &L, const SweepBuffers &B, const StepArgs &a, const PotConst &pc,
                             int precision, int stage, hipStream_t s) {
     if (pc.generic || pc.cut) return hipErrorInvalidValue;
     const ForceOut fo{B.f, B.v, B.tile_sums, a.h, a.advance};
-    return precision == SCMD_FP64 ? dispatch_ipt<SCMD_FP64>(true, stage, L, B, fo, pc, s)
-                                  : dispatch_ipt<SCMD_MIXED>(true, stage, L, B, fo, pc, s);
+    const bool energy = a.energy != 0;
+    return precision == SCMD_FP64 ? dispatch_ipt<SCMD_FP64>(true, stage, energy, L, B, fo, pc, s)
+                                  : dispatch_ipt<SCMD_MIXED>(true, stage, energy, L, B, fo, pc, s);
 }
 
 }  // namespace scmd

@@ -417,7 +417,7 @@ def test_cell_list_is_deterministic():
 # --------------------------------------------------------------------------
 # Symmetric sweeps (each unordered pair once, j tiles rotated by DPP)
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("ipt", [2, 4])
+@pytest.mark.parametrize("ipt", [2, 4, 8])
 @pytest.mark.parametrize("n", [2, 64, 65, 300, 1000, 2243, 4097])
 def test_symmetric_compute_parity(n, ipt):
     pos = inputs.c2_cooling().pos if n == 2243 else _cluster(n, seed=200 + n)
@@ -448,13 +448,14 @@ def test_symmetric_batch_parity():
         assert ens[k][0] == pytest.approx(site.sum(), rel=1e-10)
 
 
-def test_symmetric_trajectory_parity_and_determinism():
+@pytest.mark.parametrize("ipt", [4, 8])
+def test_symmetric_trajectory_parity_and_determinism(ipt):
     w = inputs.c2_cooling()
     th = w.thermostat[0]
     r_ref, v_ref, _, log = oracle.vv_run(w.pos, w.vel, 40, dt=w.dt, thermostat=th, nthreads=NT)
     outs = []
     for _ in range(2):
-        with scmd.Simulation.from_workload(w, tuning=dict(pairs=2, ipt=4)) as sim:
+        with scmd.Simulation.from_workload(w, tuning=dict(pairs=2, ipt=ipt)) as sim:
             sim.step(40)
             outs.append((sim.positions(), sim.velocities(), sim.energy()))
     np.testing.assert_array_equal(outs[0][0], outs[1][0])
@@ -626,3 +627,22 @@ def test_sampling_argument_errors():
         assert e.value.status == scmd.SCMD_EINVAL
     finally:
         scmd.scmd_destroy(ctx)
+
+
+@pytest.mark.parametrize("pairs", [2, 3])
+def test_energy_after_runs_of_every_length(pairs):
+    # the pair energy is accumulated on the last step of each run only: the
+    # energy read after runs of 1, 31, 32, 33 and 70 steps (graph replays
+    # plus remainders) must match the oracle's trajectory log
+    w = inputs.c2_cooling()
+    lens = [1, 31, 32, 33, 70]
+    _, _, _, log = oracle.vv_run(w.pos, w.vel, sum(lens), dt=w.dt, thermostat=w.thermostat[0], nthreads=NT)
+    print(f"[parity] energy after runs pairs={pairs}", flush=True)
+    with scmd.Simulation.from_workload(w, tuning=dict(pairs=pairs)) as sim:
+        done = 0
+        for n in lens:
+            sim.step(n)
+            done += n
+            e = sim.energy(0)
+            assert e[0] == pytest.approx(log[done - 1, 0], rel=1e-10), (n, done)
+            assert e[1] == pytest.approx(log[done - 1, 1], rel=1e-10), (n, done)
