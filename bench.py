@@ -177,6 +177,8 @@ def main(argv=None):
     ap.add_argument("--no-forms", action="store_true", help="skip the extra forms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--tuning", default=None,
+                    help="JSON launch-shape override for the main workload, e.g. '{\"pairs\": 2, \"ipt\": 8}'")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device once (a plain copy kernel of known "
                          "size, to scale hardware byte counters when profiling)")
@@ -191,7 +193,7 @@ def main(argv=None):
     w = _workload(args.workload)
     print(f"[bench] {w.name}: {w.n_atoms} atoms, {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
           flush=True)
-    main_res = time_gpu(w, args.steps, args.warmup)
+    main_res = time_gpu(w, args.steps, args.warmup, tuning=json.loads(args.tuning) if args.tuning else None)
     if main_res.get("roofline") is not None:
         main_res["roofline"]["traffic"] = measured_traffic(args.workload)
     print(f"[bench] {main_res['atom_steps_per_s']:.4e} atom-steps/s, {main_res['ms_per_step']:.4f} ms/step",
