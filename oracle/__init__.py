@@ -11,8 +11,11 @@ Every function is pinned by tests that do not call back into the oracle's
 own formula: the dimer and equilateral-trimer closed forms, the perfect-fcc
 lattice sums, finite differences of the energy, the net force and torque
 invariants, Mackay-icosahedron symmetry, NVE energy drift, time
-reversibility and Berendsen relaxation.  Nothing in this package is
-"parity unpinned".
+reversibility and Berendsen relaxation; the Langevin bath by the published
+Philox4x32-10 known-answer blocks, the normal law of its deviates, the
+reduction to velocity-Verlet at zero damping, the closed-form decay of a free
+atom in a bath at 0 K and the equipartition temperature of free atoms and of
+a cluster.  Nothing in this package is "parity unpinned".
 
 Arrays are numpy float64 of shape (n, 3) for positions, velocities and
 forces.  Units: Angstrom, fs, eV, u, K.
@@ -37,6 +40,7 @@ NI_MASS_U = 58.6934
 
 NVE = 0
 BERENDSEN = 1
+LANGEVIN = 2
 
 
 def build(force: bool = True) -> str:
@@ -58,7 +62,8 @@ class _Params(ctypes.Structure):
 
 class _Thermo(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("T_start", ctypes.c_double), ("T_end", ctypes.c_double),
-                ("ramp_steps", ctypes.c_int64), ("tau", ctypes.c_double)]
+                ("ramp_steps", ctypes.c_int64), ("tau", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
 
 
 _lib = None
@@ -77,6 +82,14 @@ def _configure(lib):
     lib.sco_energy.restype = dbl
     lib.sco_ndof.argtypes = [i64]
     lib.sco_ndof.restype = i64
+    lib.sco_ndof_kind.argtypes = [i64, ctypes.c_int]
+    lib.sco_ndof_kind.restype = i64
+    lib.sco_temperature_dof.argtypes = [i64, vp, dbl, i64]
+    lib.sco_temperature_dof.restype = dbl
+    lib.sco_philox4x32_10.argtypes = [vp, vp, vp]
+    lib.sco_philox4x32_10.restype = None
+    lib.sco_gauss3.argtypes = [ctypes.c_uint64, i64, i64, vp]
+    lib.sco_gauss3.restype = None
     lib.sco_kinetic.argtypes = [i64, vp, dbl]
     lib.sco_kinetic.restype = dbl
     lib.sco_temperature.argtypes = [i64, vp, dbl]
@@ -186,8 +199,29 @@ def site_energies(pos, params=None, nthreads: int = 1) -> np.ndarray:
     return out
 
 
-def ndof(n: int) -> int:
-    return int(_load().sco_ndof(n))
+def ndof(n: int, kind: int = NVE) -> int:
+    """Thermal degrees of freedom: 3N - 6 for a free cluster (1 for a dimer),
+    3N under the Langevin bath."""
+    return int(_load().sco_ndof_kind(n, kind))
+
+
+def philox4x32_10(ctr, key) -> tuple:
+    """Philox4x32-10 block of a 4-word counter under a 2-word key."""
+    c = np.ascontiguousarray([int(x) & 0xFFFFFFFF for x in ctr], dtype=np.uint32)
+    k = np.ascontiguousarray([int(x) & 0xFFFFFFFF for x in key], dtype=np.uint32)
+    if c.size != 4 or k.size != 2:
+        raise ValueError("counter has 4 words, key 2")
+    out = np.zeros(4, dtype=np.uint32)
+    _load().sco_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return tuple(int(x) for x in out)
+
+
+def gauss3(seed: int, step: int, atom: int) -> np.ndarray:
+    """The three standard normal deviates of the Langevin noise of one atom
+    at one step (numbered from 1)."""
+    out = np.zeros(3)
+    _load().sco_gauss3(int(seed) & 0xFFFFFFFFFFFFFFFF, int(step), int(atom), _ptr(out))
+    return out
 
 
 def kinetic(vel, mass_u: float = NI_MASS_U) -> float:
@@ -195,13 +229,14 @@ def kinetic(vel, mass_u: float = NI_MASS_U) -> float:
     return float(_load().sco_kinetic(len(v), _ptr(v), mass_u))
 
 
-def temperature(vel, mass_u: float = NI_MASS_U) -> float:
+def temperature(vel, mass_u: float = NI_MASS_U, kind: int = NVE) -> float:
     v = _pos(vel)
-    return float(_load().sco_temperature(len(v), _ptr(v), mass_u))
+    lib = _load()
+    return float(lib.sco_temperature_dof(len(v), _ptr(v), mass_u, lib.sco_ndof_kind(len(v), kind)))
 
 
 def target_temperature(T_start, T_end, ramp_steps, k) -> float:
-    t = _Thermo(BERENDSEN, T_start, T_end, ramp_steps, 1.0)
+    t = _Thermo(BERENDSEN, T_start, T_end, ramp_steps, 1.0, 0.0, 0)
     return float(_load().sco_target_temperature(ctypes.byref(t), k))
 
 
@@ -211,9 +246,12 @@ def berendsen_lambda(T, T_target, dt, tau) -> float:
 
 def vv_run(pos, vel, nsteps, dt=1.0, params=None, mass_u=NI_MASS_U, thermostat=None, step0=0,
            force=None, nthreads: int = 1, with_log: bool = True):
-    """Velocity-Verlet trajectory (optionally Berendsen-coupled).
+    """Velocity-Verlet trajectory, optionally thermostatted.
 
-    thermostat: None (NVE) or dict(T_start, T_end, ramp_steps, tau).
+    thermostat: None (NVE), dict(T_start, T_end, ramp_steps, tau) for
+    Berendsen, or dict(kind="langevin", T_start, T_end, ramp_steps, gamma
+    (1/ps), seed) for the Langevin bath (BAOAB; the steps of the trajectory
+    are numbered step0 + 1, step0 + 2, ... for the noise and the ramp).
     Returns (pos, vel, force, log) with log[k] = (E_pot, E_kin, T, T_target)
     of the state after step k.
     """
@@ -223,8 +261,13 @@ def vv_run(pos, vel, nsteps, dt=1.0, params=None, mass_u=NI_MASS_U, thermostat=N
     f = np.zeros((n, 3)) if force is None else _pos(force).copy()
     th = None
     if thermostat is not None:
-        th = _Thermo(BERENDSEN, float(thermostat["T_start"]), float(thermostat["T_end"]),
-                     int(thermostat.get("ramp_steps", 0)), float(thermostat["tau"]))
+        if thermostat.get("kind", "berendsen") == "langevin":
+            th = _Thermo(LANGEVIN, float(thermostat["T_start"]), float(thermostat["T_end"]),
+                         int(thermostat.get("ramp_steps", 0)), 0.0, float(thermostat["gamma"]),
+                         int(thermostat.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF)
+        else:
+            th = _Thermo(BERENDSEN, float(thermostat["T_start"]), float(thermostat["T_end"]),
+                         int(thermostat.get("ramp_steps", 0)), float(thermostat["tau"]), 0.0, 0)
     log = np.zeros((max(nsteps, 0), 4))
     p = _params(params)
     rc = _load().sco_vv_run(n, _ptr(r), _ptr(v), _ptr(f), 0 if force is None else 1, ctypes.byref(p),
@@ -244,7 +287,8 @@ def load_variant(lib_path: str):
     ns = types.SimpleNamespace(NI_PARAMS=NI_PARAMS, NI_MASS_U=NI_MASS_U)
     g = globals()
     for name in ("max_threads", "ke_conversion", "kb", "density", "forces", "forces_subset", "energy", "site_energies", "ndof",
-                 "kinetic", "temperature", "target_temperature", "berendsen_lambda", "vv_run"):
+                 "kinetic", "temperature", "target_temperature", "berendsen_lambda", "vv_run", "philox4x32_10",
+                 "gauss3"):
         fn = g[name]
         def bound(*a, _fn=fn, **k):
             global _lib

@@ -26,6 +26,11 @@
  *   - Berendsen thermostat with a linear target ramp: not in the paper (the
  *     paper uses Langevin); it is the deterministic thermostat of the
  *     cooling workloads this library runs.
+ *   - Langevin thermostat (Sec. 2, "Computational approach": damping
+ *     constant 10 1/ps), integrated with the BAOAB splitting; the noise is
+ *     Philox4x32-10 with a Box-Muller transform, keyed by (seed, step, atom)
+ *     so that any implementation of the same definition draws the same
+ *     numbers (see sco_gauss3).
  *   - Shifted cutoff: not in the paper (which runs all-pairs and calls a
  *     cutoff future work); both power sums are shifted to zero at rc and the
  *     forces are the exact gradient of that shifted energy.
@@ -237,6 +242,80 @@ double sco_berendsen_lambda(double T, double T_target, double dt, double tau) {
     return x > 0.0 ? sqrt(x) : 0.0;
 }
 
+/* Degrees of freedom by thermostat: the Langevin bath exchanges momentum and
+ * angular momentum with the cluster, so all 3N are thermal; the
+ * deterministic kinds conserve both (3N - 6). */
+int64_t sco_ndof_kind(int64_t n, int kind) {
+    if (kind == SCO_LANGEVIN) return 3 * n;
+    return sco_ndof(n);
+}
+
+double sco_temperature_dof(int64_t n, const double *vel, double mass_u, int64_t dof) {
+    if (dof <= 0) return 0.0;
+    return 2.0 * sco_kinetic(n, vel, mass_u) / ((double)dof * SCO_KB_EV_PER_K);
+}
+
+/*
+ * Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC'11): a 128-bit counter (four 32-bit words) is passed
+ * ten times through the Philox round under a 64-bit key.  A round multiplies
+ * words 0 and 2 by the two Philox multipliers into 64-bit products and
+ * rebuilds the block as
+ *   (hi(M1 c2) ^ c1 ^ k0,  lo(M1 c2),  hi(M0 c0) ^ c3 ^ k1,  lo(M0 c0));
+ * between rounds the key words are advanced by the two Weyl increments
+ * (the golden ratio and sqrt(3) - 1, as 32-bit fractions).
+ */
+#define SCO_PHILOX_M0 0xD2511F53u
+#define SCO_PHILOX_M1 0xCD9E8D57u
+#define SCO_PHILOX_W0 0x9E3779B9u
+#define SCO_PHILOX_W1 0xBB67AE85u
+
+void sco_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += SCO_PHILOX_W0;
+            k1 += SCO_PHILOX_W1;
+        }
+        const uint64_t p0 = (uint64_t)SCO_PHILOX_M0 * (uint64_t)c[0];
+        const uint64_t p1 = (uint64_t)SCO_PHILOX_M1 * (uint64_t)c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n1 = (uint32_t)p1;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        const uint32_t n3 = (uint32_t)p0;
+        c[0] = n0;
+        c[1] = n1;
+        c[2] = n2;
+        c[3] = n3;
+    }
+    memcpy(out, c, sizeof(c));
+}
+
+/*
+ * Langevin noise of one atom at one step: three independent standard normal
+ * deviates.  One Philox4x32-10 block, key (seed mod 2^32, seed div 2^32),
+ * counter (atom, 0, step mod 2^32, step div 2^32); each word w becomes the
+ * uniform u = (w + 1/2) / 2^32 in (0, 1), and the Box-Muller transform turns
+ * (u0, u1) into sqrt(-2 ln u0) (cos 2 pi u1, sin 2 pi u1) and u2, u3 into
+ * sqrt(-2 ln u2) cos 2 pi u3.
+ */
+void sco_gauss3(uint64_t seed, int64_t step, int64_t atom, double out[3]) {
+    const uint64_t st = (uint64_t)step;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const uint32_t ctr[4] = {(uint32_t)atom, 0u, (uint32_t)st, (uint32_t)(st >> 32)};
+    uint32_t w[4];
+    sco_philox4x32_10(ctr, key, w);
+    double u[4];
+    for (int k = 0; k < 4; ++k) u[k] = ((double)w[k] + 0.5) / 4294967296.0;
+    const double two_pi = 6.283185307179586476925286766559;
+    const double ra = sqrt(-2.0 * log(u[0]));
+    const double rb = sqrt(-2.0 * log(u[2]));
+    out[0] = ra * cos(two_pi * u[1]);
+    out[1] = ra * sin(two_pi * u[1]);
+    out[2] = rb * cos(two_pi * u[3]);
+}
+
 /*
  * Velocity-Verlet trajectory.  On entry pos/vel hold r(t0), v(t0) (n x 3,
  * row-major); force holds F(r(t0)) when have_force is set, else it is
@@ -244,6 +323,16 @@ double sco_berendsen_lambda(double T, double T_target, double dt, double tau) {
  *   v += (dt/2m) F;  r += dt v;  F = F(r);  v += (dt/2m) F;
  *   then, for the Berendsen kind, T from v, the target of the completed
  *   step index (step0 + k), and v *= lambda.
+ * The Langevin kind (the paper's thermostat, Sec. 2 "Computational
+ * approach": damping constant gamma) replaces the drift by the BAOAB
+ * splitting of Leimkuhler and Matthews: for the step numbered s (the steps
+ * of a trajectory count from 1, s = step0 + k + 1)
+ *   v += (dt/2m) F;  r += (dt/2) v;
+ *   v = c1 v + c2 xi_s  with c1 = exp(-gamma dt),
+ *                       c2 = sqrt((1 - c1^2) k_B T_target(s) / m),
+ *                       xi_s from sco_gauss3(seed, s, atom);
+ *   r += (dt/2) v;  F = F(r);  v += (dt/2m) F;
+ * and T counts 3N degrees of freedom.
  * Per step k (0-based in this call) the log receives, when not NULL,
  *   log[4k + 0] = E_pot, [1] = E_kin, [2] = T, [3] = T_target,
  * all of the state after the thermostat has acted.
@@ -252,21 +341,38 @@ int sco_vv_run(int64_t n, double *pos, double *vel, double *force, int have_forc
                double mass_u, double dt, int64_t nsteps, const sco_thermostat *thermo, int64_t step0,
                double *log, int nthreads) {
     if (n < 0 || nsteps < 0 || !(dt > 0.0) || !(mass_u > 0.0)) return -1;
+    const int langevin = thermo && thermo->kind == SCO_LANGEVIN;
+    if (langevin && !(thermo->gamma >= 0.0)) return -1;
     double h = 0.5 * dt / (mass_u * SCO_KE_EV_PER_U_A2_FS2);
+    const int64_t dof = sco_ndof_kind(n, thermo ? thermo->kind : SCO_NVE);
     double *site = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     if (!have_force) sco_forces(n, pos, p, force, NULL, NULL, nthreads);
     for (int64_t k = 0; k < nsteps; ++k) {
+        double Tt = 0.0;
         for (int64_t i = 0; i < 3 * n; ++i) vel[i] += h * force[i];
-        for (int64_t i = 0; i < 3 * n; ++i) pos[i] += dt * vel[i];
+        if (langevin) {
+            const int64_t s = step0 + k + 1;
+            Tt = sco_target_temperature(thermo, s);
+            const double c1 = exp(-thermo->gamma * 1e-3 * dt); /* gamma in 1/ps, dt in fs */
+            const double c2 = sqrt((1.0 - c1 * c1) * SCO_KB_EV_PER_K * Tt / (mass_u * SCO_KE_EV_PER_U_A2_FS2));
+            for (int64_t i = 0; i < 3 * n; ++i) pos[i] += 0.5 * dt * vel[i];
+            for (int64_t i = 0; i < n; ++i) {
+                double xi[3];
+                sco_gauss3(thermo->seed, s, i, xi);
+                for (int d = 0; d < 3; ++d) vel[3 * i + d] = c1 * vel[3 * i + d] + c2 * xi[d];
+            }
+            for (int64_t i = 0; i < 3 * n; ++i) pos[i] += 0.5 * dt * vel[i];
+        } else {
+            for (int64_t i = 0; i < 3 * n; ++i) pos[i] += dt * vel[i];
+        }
         sco_forces(n, pos, p, force, NULL, site, nthreads);
         for (int64_t i = 0; i < 3 * n; ++i) vel[i] += h * force[i];
-        double T = sco_temperature(n, vel, mass_u);
-        double Tt = 0.0;
+        double T = sco_temperature_dof(n, vel, mass_u, dof);
         if (thermo && thermo->kind == SCO_BERENDSEN) {
             Tt = sco_target_temperature(thermo, step0 + k + 1);
             double lam = sco_berendsen_lambda(T, Tt, dt, thermo->tau);
             for (int64_t i = 0; i < 3 * n; ++i) vel[i] *= lam;
-            T = sco_temperature(n, vel, mass_u);
+            T = sco_temperature_dof(n, vel, mass_u, dof);
         }
         if (log) {
             double u = 0.0;

@@ -25,14 +25,16 @@ typedef struct {
     double rc;  /* cutoff radius; <= 0 means all pairs, no cutoff */
 } sco_params;
 
-enum { SCO_NVE = 0, SCO_BERENDSEN = 1 };
+enum { SCO_NVE = 0, SCO_BERENDSEN = 1, SCO_LANGEVIN = 2 };
 
 typedef struct {
-    int kind;           /* SCO_NVE or SCO_BERENDSEN */
+    int kind;           /* SCO_NVE, SCO_BERENDSEN or SCO_LANGEVIN */
     double T_start;     /* K */
     double T_end;       /* K */
     int64_t ramp_steps; /* linear ramp length in steps */
     double tau;         /* Berendsen coupling time, fs */
+    double gamma;       /* Langevin damping constant, 1/ps */
+    uint64_t seed;      /* Langevin noise key */
 } sco_thermostat;
 
 double sco_ke_conversion(void);
@@ -47,6 +49,11 @@ void sco_forces_subset(int64_t n, const double *pos, const sco_params *p, const 
 double sco_energy(int64_t n, const double *pos, const sco_params *p, double *site_energy, int nthreads);
 
 int64_t sco_ndof(int64_t n);
+int64_t sco_ndof_kind(int64_t n, int kind);
+double sco_temperature_dof(int64_t n, const double *vel, double mass_u, int64_t dof);
+
+void sco_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void sco_gauss3(uint64_t seed, int64_t step, int64_t atom, double out[3]);
 double sco_kinetic(int64_t n, const double *vel, double mass_u);
 double sco_temperature(int64_t n, const double *vel, double mass_u);
 double sco_target_temperature(const sco_thermostat *t, int64_t k);

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+import test_oracle_langevin as lpins
 import test_oracle_pins as pins
 from paper_1210_3559_amd import inputs
 
@@ -27,6 +28,15 @@ MUTANTS = {
     "berendsen_ratio": ("(T_target / T - 1.0)", "(T / T_target - 1.0)"),
     "shift_sign": ("if (p->rc > 0.0) v -= pow(", "if (p->rc > 0.0) v += pow("),
     "ke_half": ("return 0.5 * mass_u * s *", "return mass_u * s *"),
+    "langevin_gamma_units": ("exp(-thermo->gamma * 1e-3 * dt)", "exp(-thermo->gamma * dt)"),
+    "langevin_c2_variance": ("sqrt((1.0 - c1 * c1) * SCO_KB", "sqrt((1.0 - c1) * SCO_KB"),
+    "langevin_half_drifts_doubled": ("pos[i] += 0.5 * dt * vel[i];", "pos[i] += dt * vel[i];"),
+    "langevin_ndof": ("if (kind == SCO_LANGEVIN) return 3 * n;", "if (kind == SCO_LANGEVIN) return 3 * n - 6;"),
+    "langevin_ramp_index": ("Tt = sco_target_temperature(thermo, s);", "Tt = sco_target_temperature(thermo, s - 1);"),
+    "philox_key_increment": ("k1 += SCO_PHILOX_W1;", "k1 += SCO_PHILOX_W0;"),
+    "philox_word_order": ("const uint32_t n1 = (uint32_t)p1;", "const uint32_t n1 = (uint32_t)p0;"),
+    "box_muller_pair": ("out[1] = ra * sin(two_pi * u[1]);", "out[1] = ra * cos(two_pi * u[1]);"),
+    "noise_ignores_step": ("(uint32_t)atom, 0u, (uint32_t)st,", "(uint32_t)atom, 0u, (uint32_t)atom,"),
     "ramp_index": ("t->T_start + (t->T_end - t->T_start) * (double)kk", "t->T_end + (t->T_start - t->T_end) * (double)kk"),
 }
 
@@ -65,6 +75,14 @@ def _pin_calls():
         lambda o: pins.test_dimer_harmonic_period(o),
         lambda o: pins.test_berendsen_relaxes_to_target(o, ni147),
         lambda o: pins.test_time_reversibility(o, ni147),
+        lambda o: lpins.test_philox_known_answers(o),
+        lambda o: lpins.test_noise_is_standard_normal(o),
+        lambda o: lpins.test_noise_box_muller_structure(o),
+        lambda o: lpins.test_zero_damping_is_velocity_verlet(o),
+        lambda o: lpins.test_free_atom_decays_in_a_cold_bath(o, 1.0),
+        lambda o: lpins.test_free_atoms_reach_bath_temperature(o),
+        lambda o: lpins.test_noise_follows_the_step_count(o),
+        lambda o: lpins.test_cluster_reaches_bath_temperature(o),
     ]
     return calls
 
