@@ -10,9 +10,11 @@
  *   - the forces -grad U, evaluated as two all-pairs sweeps: first every
  *     rho_i, then the forces (Sec. 2, "Computational approach");
  *   - Verlet time stepping, read as velocity-Verlet (same section, last
- *     paragraph), with an optional Berendsen thermostat following a linear
- *     temperature ramp (the cooling runs of the paper's workloads are driven
- *     this way here; the paper's own Langevin thermostat is not provided);
+ *     paragraph), with an optional thermostat following a linear
+ *     temperature ramp: the paper's Langevin bath (same paragraph: damping
+ *     constant gamma), integrated with the BAOAB splitting, or a
+ *     deterministic Berendsen rescaling (the cooling runs of the benchmark
+ *     workloads are driven this way);
  *   - optionally the potential truncated at rc with both power sums shifted
  *     to zero there (not in the paper, which calls a cutoff future work),
  *     evaluated with a cell list.
@@ -87,7 +89,7 @@ enum {
 enum {
     SCMD_NVE = 0,       /* no thermostat                                             */
     SCMD_BERENDSEN = 1, /* velocity rescaling towards a linear ramp T_start -> T_end */
-    SCMD_LANGEVIN = 2   /* the paper's thermostat; not provided (SCMD_EUNSUPPORTED)  */
+    SCMD_LANGEVIN = 2   /* the paper's Langevin bath (set with scmd_set_langevin)     */
 };
 
 /* Sutton-Chen parameters (Sec. 2.1).  Ni: eps = 1.5707e-2 eV, a = 3.52 A,
@@ -176,9 +178,33 @@ int scmd_set_integrator(scmd_ctx *ctx, double dt_fs, int precision, int neighbou
  * (K = ramp_steps; K <= 0 means T_end at once), lambda =
  * sqrt(1 + (dt/tau)(target/T_k - 1)) (1 when T_k = 0, 0 when the radicand is
  * negative), v <- lambda v.  tau_fs > 0; temperatures >= 0.  SCMD_NVE
- * ignores the other arguments.  SCMD_LANGEVIN returns SCMD_EUNSUPPORTED. */
+ * ignores the other arguments.  SCMD_LANGEVIN returns SCMD_EINVAL (its
+ * parameters differ: use scmd_set_langevin). */
 int scmd_set_thermostat(scmd_ctx *ctx, int cluster, int kind, double T_start_K, double T_end_K,
                         int64_t ramp_steps, double tau_fs);
+
+/* Langevin bath of one cluster (cluster = -1: every cluster), the paper's
+ * thermostat (Sec. 2, "Computational approach": damping constant 10 1/ps at
+ * a 1 fs step).  Each step, numbered s = k + 1 when k steps of the cluster
+ * are complete (counted since init, carried by checkpoints), is BAOAB:
+ *   v += (dt/2m) F;  r += (dt/2) v;
+ *   v = c1 v + c2 xi,  c1 = exp(-gamma dt),
+ *                      c2 = sqrt((1 - c1^2) k_B T_target(s) / m);
+ *   r += (dt/2) v;  F = F(r);  v += (dt/2m) F;
+ * with T_target(s) = T_start + (T_end - T_start) min(s, K)/K (K =
+ * ramp_steps; K <= 0: T_end).  xi is three standard normal deviates per
+ * atom: the Philox4x32-10 block (Salmon et al., SC'11) of key (seed mod 2^32,
+ * seed div 2^32) and counter (atom index within its cluster, 0, s mod 2^32,
+ * s div 2^32), its words w mapped to u = (w + 1/2) 2^-32 and through the
+ * Box-Muller transform: sqrt(-2 ln u0)(cos 2 pi u1, sin 2 pi u1),
+ * sqrt(-2 ln u2) cos 2 pi u3.  The noise therefore depends only on (seed,
+ * s, atom): not on the launch shape, the precision form or how steps are
+ * split into calls; give clusters different seeds for independent baths.
+ * The temperature of such a cluster counts ndof = 3N.  gamma_per_ps >= 0
+ * (0 gives velocity-Verlet with the BAOAB rounding), temperatures finite
+ * and >= 0. */
+int scmd_set_langevin(scmd_ctx *ctx, int cluster, double T_start_K, double T_end_K, int64_t ramp_steps,
+                      double gamma_per_ps, uint64_t seed);
 
 /* Override the sweep launch shape (NULL restores defaults). */
 int scmd_set_tuning(scmd_ctx *ctx, const scmd_tuning *tuning);

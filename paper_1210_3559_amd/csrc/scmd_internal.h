@@ -51,6 +51,9 @@ struct ClusterDesc {
     int32_t pad;
     double T_start, T_end, tau;
     int64_t ramp;
+    double gamma;       // Langevin damping constant, 1/ps
+    double bath_c1;     // Langevin exp(-gamma dt) (set by the host for the current dt)
+    uint64_t seed;      // Langevin noise key
 };
 
 // Mutable per-cluster state (device).
@@ -186,7 +189,8 @@ constexpr int kRowStageMax = 4096;  // clusters up to this size are staged in LD
 // stores it in st->lambda for the force sweep, whose epilogue (fused = 1)
 // applies lambda and the first half-kick and stores the positions.
 struct RowDrift {
-    int mode;   // 0: positions as they are; 1: drift with st->lambda; 2: new lambda, then drift
+    int mode;   // 0: positions as they are; 1: drift with st->lambda; 2: new lambda, then drift;
+                // 3: Langevin, the stored (r, v) are already drifted
     int local;  // mode 2: steps completed in this run (ramp index st->step + local)
 };
 // The drifted position is evaluated as p + (dt lambda) v with p = r + (dt h) F:
@@ -194,8 +198,18 @@ struct RowDrift {
 // fused force epilogue (48 bytes per atom), with the same rounding.
 hipError_t launch_row_density(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, const RowDrift &dr,
                               const PotConst &pc, int precision, hipStream_t s);
-hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, int fused,
+// fused = 1: Berendsen/NVE epilogue (lambda, both half-kicks, next drift
+// inputs); fused = 2: Langevin epilogue (second half-kick of the stored
+// post-bath velocity, then the first half-kick and the A, O, A of the next
+// step, whose drifted (r, v) are stored for mode 3).  local = steps of this
+// run completed before this one (the step is st->step + local + 1).
+hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, int fused, int local,
                             const PotConst &pc, int precision, hipStream_t s);
+// Langevin, single cluster, first step of a run: the first half-kick (after
+// the pending thermostat factor) and the A, O, A of step st->step + 1, stored
+// as the drifted (r, v) pairs that mode 3 reads.
+hipError_t launch_bath_prep(const StepArgs &a, const double4 *rp, const double4 *v, const double4 *f,
+                            double2 *dpv, int natoms, hipStream_t s);
 
 // Per-cluster energies, temperature and thermostat factor from the tile sums;
 // step_add = steps completed since the cluster step counter was last stored
@@ -207,8 +221,11 @@ hipError_t launch_drift_fin(const StepArgs &a, const double *tile_sums, int loca
                             const double4 *f, int natoms, hipStream_t s);
 
 
-hipError_t launch_drift(const int32_t *atom_cluster, const ClusterState *st, double4 *rp, double4 *v,
-                        const double4 *f, int natoms, double dt, double h, hipStream_t s);
+// Drift of every atom: v <- lambda v + (dt/2m) F, then r <- r + dt v, or
+// for a cluster in a Langevin bath the A, O, A of its step st.step + local + 1.
+hipError_t launch_drift(const int32_t *atom_cluster, const ClusterDesc *cd, const ClusterState *st, double4 *rp,
+                        double4 *v, const double4 *f, int natoms, double mass_u, double dt, double h, int local,
+                        hipStream_t s);
 hipError_t launch_aos_from4(const double4 *src, double *dst, int natoms, hipStream_t s);
 // Append the state of every cluster to ring slot `slot` (5 doubles per
 // cluster: step, E_pot, E_kin, T, T_target).

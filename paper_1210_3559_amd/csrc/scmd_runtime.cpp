@@ -167,6 +167,10 @@ int64_t ndof_of(int64_t n) {
     return 0;
 }
 
+// Thermal degrees of freedom: the Langevin bath exchanges momentum and
+// angular momentum with the cluster, so all 3N are thermal under it.
+int64_t ndof_for(int kind, int64_t n) { return kind == SCMD_LANGEVIN ? 3 * n : ndof_of(n); }
+
 PotConst make_pot(const scmd_sc_params &p) {
     PotConst pc{};
     pc.n = p.n;
@@ -270,6 +274,17 @@ bool shape_supported(int ipt, int wi, int wj) {
 
 // Symmetric plan: 64-atom tiles, groups of IPT tiles, one diagonal item per
 // group and the group's later tiles cut into chunks of about equal work.
+// Derived per-cluster constants (degrees of freedom, bath factor for the
+// current dt), then the table to the device.
+hipError_t upload_cdesc(scmd_ctx *c) {
+    for (ClusterDesc &d : c->cdesc) {
+        d.ndof = ndof_for(d.kind, d.n);
+        d.bath_c1 = d.kind == SCMD_LANGEVIN ? std::exp(-d.gamma * 1e-3 * c->dt) : 1.0;
+    }
+    if (c->cdesc.empty() || !c->d_cdesc.p) return hipSuccess;
+    return hipMemcpy(c->d_cdesc.p, c->cdesc.data(), c->cdesc.size() * sizeof(ClusterDesc), hipMemcpyHostToDevice);
+}
+
 int build_sym_plan(scmd_ctx *c, int target) {
     const int ipt = c->sym_ipt;
     std::vector<SymTile> tiles;
@@ -291,7 +306,7 @@ int build_sym_plan(scmd_ctx *c, int target) {
         d.n = n;
         d.tile0 = (int)tiles.size();
         d.ntiles = nt;
-        d.ndof = ndof_of(n);
+        d.ndof = ndof_for(d.kind, n);
         for (int t = 0; t < nt; ++t) {
             SymTile T{};
             T.c = k;
@@ -351,9 +366,7 @@ int build_sym_plan(scmd_ctx *c, int target) {
     }
     if (!tiles.empty())
         HIP_TRY(c, hipMemcpy(c->d_stiles.p, tiles.data(), tiles.size() * sizeof(SymTile), hipMemcpyHostToDevice));
-    if (!c->cdesc.empty())
-        HIP_TRY(c, hipMemcpy(c->d_cdesc.p, c->cdesc.data(), c->cdesc.size() * sizeof(ClusterDesc),
-                             hipMemcpyHostToDevice));
+    HIP_TRY(c, upload_cdesc(c));
     c->plan_ok = true;
     return SCMD_OK;
 }
@@ -382,7 +395,7 @@ int build_row_plan(scmd_ctx *c, int target, std::vector<ITile> *tiles_out) {
         d.n = n;
         d.tile0 = (int)tiles.size();
         d.ntiles = (n + ni - 1) / ni;
-        d.ndof = ndof_of(n);
+        d.ndof = ndof_for(d.kind, n);
         for (int t = 0; t < d.ntiles; ++t) {
             ITile T{};
             T.c = k;
@@ -423,9 +436,7 @@ int build_row_plan(scmd_ctx *c, int target, std::vector<ITile> *tiles_out) {
         HIP_TRY(c, hipMemcpy(c->d_order.p, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         HIP_TRY(c, hipMemcpy(c->d_tiles.p, tiles.data(), tiles.size() * sizeof(ITile), hipMemcpyHostToDevice));
     }
-    if (!c->cdesc.empty())
-        HIP_TRY(c, hipMemcpy(c->d_cdesc.p, c->cdesc.data(), c->cdesc.size() * sizeof(ClusterDesc),
-                             hipMemcpyHostToDevice));
+    HIP_TRY(c, upload_cdesc(c));
     if (tiles_out) *tiles_out = tiles;
     c->plan_ok = true;
     return SCMD_OK;
@@ -495,7 +506,7 @@ int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
         d.n = n;
         d.tile0 = (int)tiles.size();
         d.ntiles = (n + tile - 1) / tile;
-        d.ndof = ndof_of(n);
+        d.ndof = ndof_for(d.kind, n);
         // split the partner range so that each wavefront keeps >= 16 partners
         int nsplit = (int)std::ceil((double)tile * (double)n / wstar);
         nsplit = std::max(1, std::min(nsplit, std::max(1, n / (16 * c->wj))));
@@ -547,9 +558,7 @@ int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
     }
     if (!tiles.empty())
         HIP_TRY(c, hipMemcpy(c->d_tiles.p, tiles.data(), tiles.size() * sizeof(ITile), hipMemcpyHostToDevice));
-    if (!c->cdesc.empty())
-        HIP_TRY(c, hipMemcpy(c->d_cdesc.p, c->cdesc.data(), c->cdesc.size() * sizeof(ClusterDesc),
-                             hipMemcpyHostToDevice));
+    HIP_TRY(c, upload_cdesc(c));
     if (tiles_out) *tiles_out = tiles;
     c->plan_ok = true;
     return SCMD_OK;
@@ -629,7 +638,7 @@ hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int adv
     } else if (c->row) {
         const RowLaunch R{c->d_tiles.p, c->d_order.p, c->d_cdesc.p, c->ntiles, c->row_waves, c->row_nmax,
                           c->row_uni_off, c->row_uni_n, c->row_uni_ni};
-        e = force ? launch_row_force(R, B, A, fused, c->pc, c->precision, s)
+        e = force ? launch_row_force(R, B, A, fused, local, c->pc, c->precision, s)
                   : launch_row_density(R, B, A, RowDrift{drift_mode, local}, c->pc, c->precision, s);
     } else if (c->neighbour == SCMD_CELLLIST) {
         e = force ? cell_list_force(c->cells, B, A, c->d_tiles.p, c->ntiles, c->tile, c->pc, c->precision, s)
@@ -696,13 +705,21 @@ hipError_t enqueue_run(scmd_ctx *c, hipStream_t s, bool capturing, int64_t nstep
     if (c->row && c->nclusters == 1 && c->row_nmax <= kRowStageMax && c->natoms > 0) {
         // two launches per step: the density sweep drifts the staged cluster
         // (after finishing the previous step's thermostat factor), the force
-        // sweep's epilogue kicks and stores the positions
+        // sweep's epilogue kicks and stores the positions.  In a Langevin
+        // bath the force epilogue also runs the next step's bath moves and
+        // stores the drifted positions (a per-atom kernel does so before the
+        // first step of the run).
+        const bool bath = c->cdesc[0].kind == SCMD_LANGEVIN;
         for (int64_t k = 0; k < nsteps; ++k) {
             // the sampled step is the last one without the pair energy
             if (capturing) c->capture_sample = (k == std::max<int64_t>(0, nsteps - 2));
             const int en = k == nsteps - 1;
-            if ((e = sweep(c, false, s, capturing, 1, 1, k == 0 ? 1 : 2, (int)k)) != hipSuccess) return e;
-            if ((e = sweep(c, true, s, capturing, 1, en, 0, 0, 1)) != hipSuccess) return e;
+            if (bath && k == 0 &&
+                (e = launch_bath_prep(A, c->rp.p, c->v.p, c->f.p, c->dpv.p, c->natoms, s)) != hipSuccess)
+                return e;
+            const int mode = bath ? 3 : (k == 0 ? 1 : 2);
+            if ((e = sweep(c, false, s, capturing, 1, 1, mode, (int)k)) != hipSuccess) return e;
+            if ((e = sweep(c, true, s, capturing, 1, en, 0, (int)k, bath ? 2 : 1)) != hipSuccess) return e;
         }
         c->capture_sample = false;
         if (nsteps > 0) return launch_finalize(A, c->d_tile_sums.p, c->nclusters, (int)nsteps, s);
@@ -710,11 +727,12 @@ hipError_t enqueue_run(scmd_ctx *c, hipStream_t s, bool capturing, int64_t nstep
     }
     const bool fuse = c->nclusters == 1;
     for (int64_t k = 0; k < nsteps; ++k) {
+        // a batch stores the step counters after every step (local = 0)
         if (fuse && k > 0)
             e = launch_drift_fin(A, c->d_tile_sums.p, (int)k, c->rp.p, c->v.p, c->f.p, c->natoms, s);
         else
-            e = launch_drift(c->atom_cluster.p, c->d_state.p, c->rp.p, c->v.p, c->f.p, c->natoms, c->dt,
-                             half_kick(c), s);
+            e = launch_drift(c->atom_cluster.p, c->d_cdesc.p, c->d_state.p, c->rp.p, c->v.p, c->f.p, c->natoms,
+                             c->mass, c->dt, half_kick(c), 0, s);
         if (e != hipSuccess) return e;
         if (capturing) c->capture_sample = (k == std::max<int64_t>(0, nsteps - 2));
         e = enqueue_sweeps(c, s, capturing, 1, k == nsteps - 1);
@@ -876,6 +894,18 @@ struct StateHeader {
 size_t state_bytes(const scmd_ctx *c) {
     return sizeof(StateHeader) + (c->nclusters + 1) * sizeof(int64_t) + 3 * (size_t)c->natoms * sizeof(double4) +
            (size_t)c->natoms * sizeof(double) + (size_t)c->nclusters * (sizeof(ClusterDesc) + sizeof(ClusterState));
+}
+
+// After a thermostat setting changed: the device table (when a plan holds
+// one) and the captured steps, which branch on the kind at capture time.
+int apply_thermostat_change(scmd_ctx *c) {
+    if (c->plan_ok && c->d_cdesc.p) {
+        HIP_TRY(c, hipSetDevice(c->device));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, upload_cdesc(c));
+    }
+    drop_graph(c);
+    return SCMD_OK;
 }
 
 }  // namespace
@@ -1116,7 +1146,7 @@ int scmd_set_thermostat(scmd_ctx *ctx, int cluster, int kind, double T_start_K, 
     if (!ctx) return SCMD_EINVAL;
     if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
     if (cluster < -1 || cluster >= ctx->nclusters) return fail(ctx, SCMD_EINVAL, "cluster index out of range");
-    if (kind == SCMD_LANGEVIN) return fail(ctx, SCMD_EUNSUPPORTED, "Langevin thermostat not provided");
+    if (kind == SCMD_LANGEVIN) return fail(ctx, SCMD_EINVAL, "the Langevin bath is set with scmd_set_langevin");
     if (kind != SCMD_NVE && kind != SCMD_BERENDSEN) return fail(ctx, SCMD_EINVAL, "unknown thermostat kind");
     if (kind == SCMD_BERENDSEN) {
         if (!(tau_fs > 0.0) || !std::isfinite(tau_fs)) return fail(ctx, SCMD_EINVAL, "need tau_fs > 0");
@@ -1134,12 +1164,28 @@ int scmd_set_thermostat(scmd_ctx *ctx, int cluster, int kind, double T_start_K, 
             d.tau = tau_fs;
         }
     }
-    if (ctx->plan_ok && ctx->d_cdesc.p) {
-        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-        HIP_TRY(ctx, hipMemcpy(ctx->d_cdesc.p, ctx->cdesc.data(), ctx->cdesc.size() * sizeof(ClusterDesc),
-                               hipMemcpyHostToDevice));
+    return apply_thermostat_change(ctx);
+}
+
+int scmd_set_langevin(scmd_ctx *ctx, int cluster, double T_start_K, double T_end_K, int64_t ramp_steps,
+                      double gamma_per_ps, uint64_t seed) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
+    if (cluster < -1 || cluster >= ctx->nclusters) return fail(ctx, SCMD_EINVAL, "cluster index out of range");
+    if (!(gamma_per_ps >= 0.0) || !std::isfinite(gamma_per_ps)) return fail(ctx, SCMD_EINVAL, "need gamma >= 0");
+    if (!(T_start_K >= 0.0) || !(T_end_K >= 0.0) || !std::isfinite(T_start_K) || !std::isfinite(T_end_K))
+        return fail(ctx, SCMD_EINVAL, "temperatures must be finite and >= 0");
+    const int a = cluster < 0 ? 0 : cluster, b = cluster < 0 ? ctx->nclusters : cluster + 1;
+    for (int k = a; k < b; ++k) {
+        ClusterDesc &d = ctx->cdesc[k];
+        d.kind = SCMD_LANGEVIN;
+        d.T_start = T_start_K;
+        d.T_end = T_end_K;
+        d.ramp = ramp_steps;
+        d.gamma = gamma_per_ps;
+        d.seed = seed;
     }
-    return SCMD_OK;
+    return apply_thermostat_change(ctx);
 }
 
 int scmd_set_tuning(scmd_ctx *ctx, const scmd_tuning *t) {
@@ -1309,7 +1355,7 @@ int scmd_get_temperature(scmd_ctx *ctx, int cluster, double *T_K, int64_t *ndof)
         rc = copy_state_table(ctx, st);
         if (rc != SCMD_OK) return rc;
         *T_K = st[cluster].temp;
-        if (ndof) *ndof = ndof_of(ctx->offsets[cluster + 1] - ctx->offsets[cluster]);
+        if (ndof) *ndof = ndof_for(ctx->cdesc[cluster].kind, ctx->offsets[cluster + 1] - ctx->offsets[cluster]);
         return SCMD_OK;
     })
 }
@@ -1393,7 +1439,7 @@ int scmd_get_state(scmd_ctx *ctx, void *buf, size_t *bytes) {
         char *p = (char *)buf;
         StateHeader h{};
         std::memcpy(h.magic, "SCMDSTA1", 8);
-        h.version = 1;
+        h.version = 2;
         h.nclusters = ctx->nclusters;
         h.natoms = ctx->natoms;
         h.step = ctx->step;
@@ -1424,7 +1470,7 @@ int scmd_set_state(scmd_ctx *ctx, const void *buf, size_t bytes) {
     if (bytes < sizeof(StateHeader)) return fail(ctx, SCMD_EINVAL, "blob too small");
     StateHeader h;
     std::memcpy(&h, buf, sizeof(h));
-    if (std::memcmp(h.magic, "SCMDSTA1", 8) != 0 || h.version != 1) return fail(ctx, SCMD_EINVAL, "not a state blob");
+    if (std::memcmp(h.magic, "SCMDSTA1", 8) != 0 || h.version != 2) return fail(ctx, SCMD_EINVAL, "not a state blob");
     if (h.nclusters != ctx->nclusters || h.natoms != ctx->natoms || bytes != state_bytes(ctx))
         return fail(ctx, SCMD_EINVAL, "blob has a different cluster layout");
     const char *p = (const char *)buf + sizeof(h);
@@ -1450,12 +1496,13 @@ int scmd_set_state(scmd_ctx *ctx, const void *buf, size_t bytes) {
             ctx->cdesc[k].T_end = cd[k].T_end;
             ctx->cdesc[k].tau = cd[k].tau;
             ctx->cdesc[k].ramp = cd[k].ramp;
+            ctx->cdesc[k].gamma = cd[k].gamma;
+            ctx->cdesc[k].seed = cd[k].seed;
         }
         p += ctx->nclusters * sizeof(ClusterDesc);
         HIP_TRY(ctx, hipMemcpy(ctx->d_state.p, p, ctx->nclusters * sizeof(ClusterState), hipMemcpyHostToDevice));
-        if (ctx->plan_ok)
-            HIP_TRY(ctx, hipMemcpy(ctx->d_cdesc.p, ctx->cdesc.data(), ctx->nclusters * sizeof(ClusterDesc),
-                                   hipMemcpyHostToDevice));
+        if (ctx->plan_ok) HIP_TRY(ctx, upload_cdesc(ctx));
+        drop_graph(ctx);
         ctx->step = h.step;
         ctx->have_forces = h.have_forces != 0;
         HIP_TRY(ctx, hipMemset(ctx->d_flag.p, 0, sizeof(int)));

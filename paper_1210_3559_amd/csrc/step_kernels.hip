@@ -2,6 +2,7 @@
 //
 // Step layout on the device (captured into a HIP graph):
 //   drift          v <- lambda v + (dt/2m) F;  r <- r + dt v      (this file)
+//                  (Langevin bath: r, v <- A, O, A of bath.h)
 //   density sweep  rho, psi, embedding energy                    (sweep kernels)
 //   force sweep    F, second half-kick, energies, thermostat     (sweep kernels)
 // Integration follows velocity-Verlet (the paper's Verlet step, Sec. 2
@@ -13,28 +14,63 @@
 namespace scmd {
 namespace {
 
-__global__ __launch_bounds__(256) void k_drift(const int32_t *__restrict__ atom_cluster,
-                                               const ClusterState *__restrict__ st, double4 *__restrict__ rp,
-                                               double4 *__restrict__ v, const double4 *__restrict__ f, int natoms,
-                                               double dt, double h) {
+// First half-kick (after the pending thermostat factor) and the move of one
+// atom: r + dt v, or the bath's A, O, A of step `step` (atom index a in its
+// cluster).
+__device__ __forceinline__ void drift_atom(const ClusterDesc &d, int64_t step, int a, double lam, double mass_u,
+                                           double dt, double h, double4 &ri, double4 &vi, const double4 &fi) {
 #pragma clang fp contract(off)
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= natoms) return;
-    const double lam = st[atom_cluster[i]].lambda;
-    double4 vi = v[i];
-    const double4 fi = f[i];
-    double4 ri = rp[i];
     vi.x = lam * vi.x;
     vi.y = lam * vi.y;
     vi.z = lam * vi.z;
     vi.x = vi.x + h * fi.x;
     vi.y = vi.y + h * fi.y;
     vi.z = vi.z + h * fi.z;
-    ri.x = ri.x + dt * vi.x;
-    ri.y = ri.y + dt * vi.y;
-    ri.z = ri.z + dt * vi.z;
+    if (d.kind == SCMD_LANGEVIN) {
+        dev::bath_drift(d, step, a, mass_u, dt, ri, vi);
+    } else {
+        ri.x = ri.x + dt * vi.x;
+        ri.y = ri.y + dt * vi.y;
+        ri.z = ri.z + dt * vi.z;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_drift(const int32_t *__restrict__ atom_cluster,
+                                               const ClusterDesc *__restrict__ cd,
+                                               const ClusterState *__restrict__ st, double4 *__restrict__ rp,
+                                               double4 *__restrict__ v, const double4 *__restrict__ f, int natoms,
+                                               double mass_u, double dt, double h, int local) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= natoms) return;
+    const int c = atom_cluster[i];
+    const ClusterState &sc = st[c];
+    const ClusterDesc &d = cd[c];
+    double4 vi = v[i];
+    const double4 fi = f[i];
+    double4 ri = rp[i];
+    drift_atom(d, sc.step + local + 1, i - d.off, sc.lambda, mass_u, dt, h, ri, vi, fi);
     v[i] = vi;
     rp[i] = ri;
+}
+
+// Langevin, single cluster: the drifted (r, v) of the first step of a run,
+// stored as the pairs (x, y), (z, vx), (vy, vz) for the row density sweep.
+__global__ __launch_bounds__(256) void k_bath_prep(const ClusterDesc *__restrict__ cd,
+                                                   const ClusterState *__restrict__ st,
+                                                   const double4 *__restrict__ rp, const double4 *__restrict__ v,
+                                                   const double4 *__restrict__ f, double2 *__restrict__ dpv,
+                                                   int natoms, double mass_u, double dt, double h) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= natoms) return;
+    const ClusterDesc &d = cd[0];
+    double4 vi = v[i];
+    const double4 fi = f[i];
+    double4 ri = rp[i];
+    drift_atom(d, st[0].step + 1, i - d.off, st[0].lambda, mass_u, dt, h, ri, vi, fi);
+    double2 *o = dpv + 3 * (size_t)i;
+    o[0] = make_double2(ri.x, ri.y);
+    o[1] = make_double2(ri.z, vi.x);
+    o[2] = make_double2(vi.y, vi.z);
 }
 
 // Drift fused with the finish of the previous step of a single cluster:
@@ -44,7 +80,6 @@ __global__ __launch_bounds__(256) void k_drift(const int32_t *__restrict__ atom_
 __global__ __launch_bounds__(256) void k_drift_fin(dev::FinalizeArgs fa, double4 *__restrict__ rp,
                                                    double4 *__restrict__ v, const double4 *__restrict__ f,
                                                    int natoms, double dt, double h) {
-#pragma clang fp contract(off)
     __shared__ double sh[12];
     __shared__ double lam_sh;
     const double l0 = dev::cluster_finalize(0, fa, sh, blockIdx.x == 0);
@@ -53,18 +88,12 @@ __global__ __launch_bounds__(256) void k_drift_fin(dev::FinalizeArgs fa, double4
     const double lam = lam_sh;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= natoms) return;
+    const ClusterDesc &d = fa.cd[0];
     double4 vi = v[i];
     const double4 fi = f[i];
     double4 ri = rp[i];
-    vi.x = lam * vi.x;
-    vi.y = lam * vi.y;
-    vi.z = lam * vi.z;
-    vi.x = vi.x + h * fi.x;
-    vi.y = vi.y + h * fi.y;
-    vi.z = vi.z + h * fi.z;
-    ri.x = ri.x + dt * vi.x;
-    ri.y = ri.y + dt * vi.y;
-    ri.z = ri.z + dt * vi.z;
+    // this drift starts step fa.step_add + 1 of the run
+    drift_atom(d, fa.st[0].step + fa.step_add + 1, i - d.off, lam, fa.mass_u, dt, h, ri, vi, fi);
     v[i] = vi;
     rp[i] = ri;
 }
@@ -94,12 +123,22 @@ __global__ __launch_bounds__(256) void k_aos_from4(const double4 *__restrict__ s
 
 }  // namespace
 
-hipError_t launch_drift(const int32_t *atom_cluster, const ClusterState *st, double4 *rp, double4 *v,
-                        const double4 *f, int natoms, double dt, double h, hipStream_t s) {
+hipError_t launch_drift(const int32_t *atom_cluster, const ClusterDesc *cd, const ClusterState *st, double4 *rp,
+                        double4 *v, const double4 *f, int natoms, double mass_u, double dt, double h, int local,
+                        hipStream_t s) {
     if (natoms <= 0) return hipSuccess;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_drift, dim3((natoms + 255) / 256), dim3(256), 0, s, atom_cluster, st, rp, v, f, natoms,
-                       dt, h);
+    hipLaunchKernelGGL(k_drift, dim3((natoms + 255) / 256), dim3(256), 0, s, atom_cluster, cd, st, rp, v, f, natoms,
+                       mass_u, dt, h, local);
+    return hipGetLastError();
+}
+
+hipError_t launch_bath_prep(const StepArgs &a, const double4 *rp, const double4 *v, const double4 *f,
+                            double2 *dpv, int natoms, hipStream_t s) {
+    if (natoms <= 0) return hipSuccess;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_bath_prep, dim3((natoms + 255) / 256), dim3(256), 0, s, a.cd, a.st, rp, v, f, dpv, natoms,
+                       a.mass_u, a.dt, a.h);
     return hipGetLastError();
 }
 

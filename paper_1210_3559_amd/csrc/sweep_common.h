@@ -5,6 +5,7 @@
 #pragma once
 
 #include "../../include/scmd.h"
+#include "bath.h"
 #include "scmd_internal.h"
 
 namespace scmd {
@@ -280,8 +281,12 @@ struct ForceOut {
     int fused;
     const ClusterState *st;
     double4 *rp;
-    double2 *dpv;  // drift inputs of the next step (p, v)
+    double2 *dpv;  // drift inputs of the next step (p, v); Langevin: the drifted (r, v)
     double dth;    // dt h
+    // Langevin epilogue (fused = 2): cluster 0's bath, the run's step index
+    const ClusterDesc *cd;
+    int local;
+    double dt, mass_u;
 };
 
 struct FinalizeArgs {
@@ -330,18 +335,16 @@ __device__ __forceinline__ KinT kinetic_temperature(const ClusterDesc &d, double
 }
 
 // Thermostat factor after a step whose ramp index is step_now, at
-// temperature T; *ttarget receives the target (0 without thermostat).
+// temperature T; *ttarget receives the target (0 without thermostat).  The
+// Langevin bath acts inside the drift: its factor is 1.
 __device__ __forceinline__ double thermostat_lambda(const ClusterDesc &d, double dt, double T, int64_t step_now,
                                                     double *ttarget) {
 #pragma clang fp contract(off)
     double lam = 1.0;
     *ttarget = 0.0;
+    if (d.kind == SCMD_LANGEVIN) *ttarget = ramp_target(d, step_now);
     if (d.kind == SCMD_BERENDSEN) {
-        double tt = d.T_end;
-        if (d.ramp > 0) {
-            const int64_t k = step_now < d.ramp ? step_now : d.ramp;
-            tt = d.T_start + (d.T_end - d.T_start) * (double)k / (double)d.ramp;
-        }
+        const double tt = ramp_target(d, step_now);
         *ttarget = tt;
         if (T > 0.0) {
             const double x = 1.0 + (dt / d.tau) * (tt / T - 1.0);

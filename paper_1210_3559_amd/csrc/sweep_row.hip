@@ -307,6 +307,38 @@ __device__ __forceinline__ void force_atom_fused(int i, double fx, double fy, do
     v2 += vi.x * vi.x + vi.y * vi.y + vi.z * vi.z;
 }
 
+// Langevin epilogue (fused = 2): the stored post-bath velocity gets the
+// second half-kick; then the first half-kick of the next step with the same
+// force and that step's A, O, A (bath.h), whose drifted (r, v) are stored for
+// the next density sweep (mode 3).  The order of operations is the same as in
+// the drift kernel.
+__device__ __forceinline__ void force_atom_bath(int i, double fx, double fy, double fz, double eu, const double4 &r,
+                                                const double4 &v_bath, const ForceOut &o, const PotConst &pc,
+                                                double &epair, double &v2) {
+#pragma clang fp contract(off)
+    const double ei = pc.half_eps_an * eu;
+    double4 vi = v_bath;
+    vi.x = vi.x + o.h * fx;
+    vi.y = vi.y + o.h * fy;
+    vi.z = vi.z + o.h * fz;
+    o.f[i] = make_double4(fx, fy, fz, ei);
+    o.v[i] = vi;
+    o.rp[i] = make_double4(r.x, r.y, r.z, 0.0);
+    epair += ei;
+    v2 += vi.x * vi.x + vi.y * vi.y + vi.z * vi.z;
+    const ClusterDesc &d = o.cd[0];
+    double4 rn = make_double4(r.x, r.y, r.z, 0.0);
+    vi.x = vi.x + o.h * fx;
+    vi.y = vi.y + o.h * fy;
+    vi.z = vi.z + o.h * fz;
+    // this is step st->step + local + 1 of the cluster; prepare the next one
+    bath_drift(d, o.st->step + o.local + 2, i - d.off, o.mass_u, o.dt, rn, vi);
+    double2 *q = o.dpv + 3 * (size_t)i;
+    q[0] = make_double2(rn.x, rn.y);
+    q[1] = make_double2(rn.z, vi.x);
+    q[2] = make_double2(vi.y, vi.z);
+}
+
 // ---------------------------------------------------------------------------
 // Density sweep
 // ---------------------------------------------------------------------------
@@ -342,7 +374,7 @@ __global__ __launch_bounds__(64 * W) void k_row_density(RowArgs ra, DensityOut o
             // stage_copy); mode 2 reads the stored (p, v), mode 1 forms p
             const double4 *gv = da.v + rt.off, *gf = da.f + rt.off;
             const double2 *gd = da.dpv + 3 * (size_t)rt.off;
-            const bool stored = da.mode == 2;
+            const bool stored = da.mode >= 2;
             auto load = [&](int a) { return stored ? pv_load(gd, a) : pv_from_rvf(src, gv, gf, a, da.dth); };
             const PV own = load(i_local);
             constexpr int T = 64 * W;
@@ -364,8 +396,9 @@ __global__ __launch_bounds__(64 * W) void k_row_density(RowArgs ra, DensityOut o
                 lam = thermostat_lambda(d, da.dt, kt.T, da.st->step + da.local, &tt);
                 if (blockIdx.x == 0 && tid == 0) da.st->lambda = lam;
             } else {
-                lam = da.st->lambda;
+                lam = da.mode == 3 ? 0.0 : da.st->lambda;
             }
+            // mode 3 stores drifted positions: p + 0 v = p
             const double dtl = da.dt * lam;
             qi = drifted(own, dtl);
             if (a0 < rt.n) lj[a0] = drifted(t0, dtl);
@@ -431,8 +464,15 @@ __global__ __launch_bounds__(64 * W) void k_row_force(RowArgs ra, const double4 
     // the epilogue's own-atom loads are issued now, off the critical path
     double4 v_own = make_double4(0, 0, 0, 0), f_own = make_double4(0, 0, 0, 0);
     if (tid < L.ni) {
-        v_own = o.v[rt.i0 + tid];
-        if (o.fused) f_own = o.f[rt.i0 + tid];
+        if (o.fused == 2) {
+            // Langevin: the post-bath velocity stored with the drifted position
+            const double2 *q = o.dpv + 3 * (size_t)(rt.i0 + tid);
+            const double2 q1 = q[1], q2 = q[2];
+            v_own = make_double4(q1.y, q2.x, q2.y, 0.0);
+        } else {
+            v_own = o.v[rt.i0 + tid];
+            if (o.fused) f_own = o.f[rt.i0 + tid];
+        }
     }
     double *sh = reinterpret_cast<double *>(lds_row);
     if constexpr (STAGE) {
@@ -451,7 +491,9 @@ __global__ __launch_bounds__(64 * W) void k_row_force(RowArgs ra, const double4 
     double epair = 0.0, v2 = 0.0;
     if (tid < L.ni) {
         const int i = rt.i0 + tid;
-        if (o.fused)
+        if (o.fused == 2)
+            force_atom_bath(i, v[0], v[1], v[2], v[3], src[i - rt.off], v_own, o, pc, epair, v2);
+        else if (o.fused)
             force_atom_fused(i, v[0], v[1], v[2], v[3], src[i - rt.off], v_own, f_own, o, pc, epair, v2);
         else
             force_atom_v(i, v[0], v[1], v[2], v[3], v_own, o, pc, epair, v2);
@@ -537,12 +579,12 @@ hipError_t launch_row_density(const RowLaunch &L, const SweepBuffers &B, const S
     return row_dispatch(false, true, L, B, fo, da, pc, precision, s);
 }
 
-hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, int fused,
+hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, int fused, int local,
                             const PotConst &pc, int precision, hipStream_t s) {
     // the fused epilogue stores the drifted positions (rp is the context's
     // writable position array; the sweeps otherwise only read it)
-    const ForceOut fo{B.f, B.v, B.tile_sums, a.h, a.advance, fused, a.st, const_cast<double4 *>(B.rp), B.dpv,
-                      a.dt * a.h};
+    const ForceOut fo{B.f,  B.v,       B.tile_sums, a.h,  a.advance, fused,    a.st, const_cast<double4 *>(B.rp),
+                      B.dpv, a.dt * a.h, a.cd,       local, a.dt,      a.mass_u};
     const RowDriftArgs da{};
     return row_dispatch(true, a.energy != 0, L, B, fo, da, pc, precision, s);
 }

@@ -41,7 +41,8 @@ SCMD_KERNEL_FORCE = 1
 # Every symbol include/scmd.h declares.
 EXPORTS = (
     "scmd_abi_version", "scmd_status_string", "scmd_create", "scmd_destroy", "scmd_init_clusters",
-    "scmd_set_potential", "scmd_set_integrator", "scmd_set_thermostat", "scmd_set_tuning", "scmd_compute",
+    "scmd_set_potential", "scmd_set_integrator", "scmd_set_thermostat", "scmd_set_langevin", "scmd_set_tuning",
+    "scmd_compute",
     "scmd_step", "scmd_step_async", "scmd_synchronize", "scmd_get_step", "scmd_get_energy",
     "scmd_get_temperature", "scmd_get_positions", "scmd_get_velocities", "scmd_get_forces", "scmd_get_density",
     "scmd_get_forces_device", "scmd_get_state", "scmd_set_state", "scmd_set_profiling", "scmd_get_kernel_time",
@@ -94,6 +95,7 @@ def load(path: str = LIB_PATH):
         "scmd_set_potential": (i32, [vp, ctypes.POINTER(_Params)]),
         "scmd_set_integrator": (i32, [vp, dbl, i32, i32]),
         "scmd_set_thermostat": (i32, [vp, i32, i32, dbl, dbl, i64, dbl]),
+        "scmd_set_langevin": (i32, [vp, i32, dbl, dbl, i64, dbl, ctypes.c_uint64]),
         "scmd_set_tuning": (i32, [vp, ctypes.POINTER(_Tuning)]),
         "scmd_compute": (i32, [vp]),
         "scmd_step": (i32, [vp, i64]),
@@ -189,6 +191,12 @@ def scmd_set_thermostat(ctx, cluster: int, kind: int, T_start_K: float = 0.0, T_
                         ramp_steps: int = 0, tau_fs: float = 100.0) -> None:
     _check(ctx, load().scmd_set_thermostat(ctx, int(cluster), int(kind), float(T_start_K), float(T_end_K),
                                            int(ramp_steps), float(tau_fs)))
+
+
+def scmd_set_langevin(ctx, cluster: int, T_start_K: float, T_end_K: float, ramp_steps: int = 0,
+                      gamma_per_ps: float = 10.0, seed: int = 0) -> None:
+    _check(ctx, load().scmd_set_langevin(ctx, int(cluster), float(T_start_K), float(T_end_K), int(ramp_steps),
+                                         float(gamma_per_ps), int(seed) & 0xFFFFFFFFFFFFFFFF))
 
 
 def scmd_set_tuning(ctx, ipt: int = 0, waves_i: int = 0, waves_j: int = 0, target_items: int = 0,
@@ -337,8 +345,7 @@ class Simulation:
                 scmd_set_tuning(self.ctx, **tuning)
             for k, th in enumerate(thermostats or []):
                 if th is not None:
-                    scmd_set_thermostat(self.ctx, k, SCMD_BERENDSEN, th["T_start"], th["T_end"],
-                                        th.get("ramp_steps", 0), th["tau"])
+                    self.set_thermostat(k, th)
         except Exception:
             scmd_destroy(self.ctx)
             self.ctx = None
@@ -389,6 +396,18 @@ class Simulation:
 
     def temperature(self, cluster: int = 0):
         return scmd_get_temperature(self.ctx, cluster)
+
+    def set_thermostat(self, cluster: int, th: dict | None):
+        """th: None (NVE), dict(T_start, T_end, ramp_steps, tau) for Berendsen,
+        or dict(kind="langevin", T_start, T_end, ramp_steps, gamma, seed)."""
+        if th is None:
+            scmd_set_thermostat(self.ctx, cluster, SCMD_NVE)
+        elif th.get("kind", "berendsen") == "langevin":
+            scmd_set_langevin(self.ctx, cluster, th["T_start"], th["T_end"], th.get("ramp_steps", 0),
+                              th.get("gamma", 10.0), th.get("seed", 0))
+        else:
+            scmd_set_thermostat(self.ctx, cluster, SCMD_BERENDSEN, th["T_start"], th["T_end"],
+                                th.get("ramp_steps", 0), th["tau"])
 
     def set_sampling(self, every: int, capacity: int = 1024):
         scmd_set_sampling(self.ctx, every, capacity)

@@ -296,7 +296,7 @@ def test_call_order_and_argument_errors():
         scmd.scmd_set_integrator(ctx, 1.0)
         with pytest.raises(scmd.ScmdError) as e:
             scmd.scmd_set_thermostat(ctx, 0, scmd.SCMD_LANGEVIN, 300, 300, 0, 100)
-        assert e.value.status == scmd.SCMD_EUNSUPPORTED
+        assert e.value.status == scmd.SCMD_EINVAL
         with pytest.raises(scmd.ScmdError) as e:
             scmd.scmd_set_thermostat(ctx, 3, scmd.SCMD_BERENDSEN, 300, 300, 0, 100)
         assert e.value.status == scmd.SCMD_EINVAL
