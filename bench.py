@@ -216,7 +216,8 @@ def main(argv=None):
                 ("allpairs_fp64_ni48077", "ni48077_allpairs", None), ("allpairs_fp64_ni50000", "ni50000_allpairs", None),
                 ("mixed_ni15000", "ni15000_mixed", None), ("fp64_ni15000", "ni15000_fp64", None),
                 ("batched_fp64_256", "batch256", None), ("batched_mixed_256", "batch256_mixed", None),
-                ("cell_fp64_ni48077", "ni48077_cell", None)]
+                ("cell_fp64_ni48077", "ni48077_cell", None),
+                ("langevin_fp64_ni2243", "ni2243_langevin", None), ("langevin_batched_fp64_256", "batch256_langevin", None)]
         for key, name, prec in plan:
             if name is None:
                 forms[key] = {k: main_res[k] for k in ("atom_steps_per_s", "pair_interactions_per_s", "ms_per_step")}

@@ -67,16 +67,21 @@ __device__ __forceinline__ double ramp_target(const ClusterDesc &d, int64_t k) {
     return d.T_start + (d.T_end - d.T_start) * (double)kk / (double)d.ramp;
 }
 
-// A, O, A of step `step` for one atom whose velocity v has had the first
-// half-kick: updates r and v in place.
-__device__ __forceinline__ void bath_drift(const ClusterDesc &d, int64_t step, int atom, double mass_u, double dt,
-                                           double4 &r, double4 &v) {
+// Noise amplitude c2 of step `step`.
+__device__ __forceinline__ double bath_c2(const ClusterDesc &d, int64_t step, double mass_u) {
+#pragma clang fp contract(off)
+    const double c1 = d.bath_c1;
+    const double tt = ramp_target(d, step);
+    return sqrt((1.0 - c1 * c1) * kBoltzmannEv * tt / (mass_u * kEvPerUA2Fs2));
+}
+
+// A, O, A for one atom whose velocity v has had the first half-kick, with
+// its noise xi and the step's amplitude c2 given: updates r and v in place.
+__device__ __forceinline__ void bath_drift_xi(const ClusterDesc &d, double c2, const double3 &xi, double dt,
+                                              double4 &r, double4 &v) {
 #pragma clang fp contract(off)
     const double hdt = 0.5 * dt;
     const double c1 = d.bath_c1;
-    const double tt = ramp_target(d, step);
-    const double c2 = sqrt((1.0 - c1 * c1) * kBoltzmannEv * tt / (mass_u * kEvPerUA2Fs2));
-    const double3 xi = bath_noise(d.seed, step, atom);
     r.x = r.x + hdt * v.x;
     r.y = r.y + hdt * v.y;
     r.z = r.z + hdt * v.z;
@@ -86,6 +91,11 @@ __device__ __forceinline__ void bath_drift(const ClusterDesc &d, int64_t step, i
     r.x = r.x + hdt * v.x;
     r.y = r.y + hdt * v.y;
     r.z = r.z + hdt * v.z;
+}
+
+__device__ __forceinline__ void bath_drift(const ClusterDesc &d, int64_t step, int atom, double mass_u, double dt,
+                                           double4 &r, double4 &v) {
+    bath_drift_xi(d, bath_c2(d, step, mass_u), bath_noise(d.seed, step, atom), dt, r, v);
 }
 
 }  // namespace dev

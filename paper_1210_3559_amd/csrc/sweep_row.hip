@@ -218,21 +218,32 @@ __device__ __forceinline__ void row_loop(const RowLayout &L, const double4 *__re
 // (named registers: an array here would live in scratch), so four atoms per
 // thread cost one memory round trip.  All workgroups read the same atoms, so
 // the copy is bound by the L2-to-CU bandwidth (bytes per atom x workgroups).
-template <int W>
-__device__ __forceinline__ void stage_copy(double4 *lj, const double4 *__restrict__ g, int n) {
+// `mid` runs between the first loads and their stores (in every thread with
+// threadIdx.x < n): ALU work placed there overlaps the memory round trip.
+template <int W, typename Mid>
+__device__ __forceinline__ void stage_copy(double4 *lj, const double4 *__restrict__ g, int n, Mid &&mid) {
     constexpr int T = 64 * W;
+    bool first = true;
     for (int a0 = threadIdx.x; a0 < n; a0 += 4 * T) {
         const int a1 = a0 + T, a2 = a1 + T, a3 = a2 + T;
         double4 t0 = g[a0], t1, t2, t3;
         if (a1 < n) t1 = g[a1];
         if (a2 < n) t2 = g[a2];
         if (a3 < n) t3 = g[a3];
+        if (first) {
+            mid();
+            first = false;
+        }
         lj[a0] = t0;
         if (a1 < n) lj[a1] = t1;
         if (a2 < n) lj[a2] = t2;
         if (a3 < n) lj[a3] = t3;
     }
     __syncthreads();
+}
+template <int W>
+__device__ __forceinline__ void stage_copy(double4 *lj, const double4 *__restrict__ g, int n) {
+    stage_copy<W>(lj, g, n, [] {});
 }
 
 // Drift arguments of the density sweep (see RowDrift).
@@ -313,8 +324,8 @@ __device__ __forceinline__ void force_atom_fused(int i, double fx, double fy, do
 // the next density sweep (mode 3).  The order of operations is the same as in
 // the drift kernel.
 __device__ __forceinline__ void force_atom_bath(int i, double fx, double fy, double fz, double eu, const double4 &r,
-                                                const double4 &v_bath, const ForceOut &o, const PotConst &pc,
-                                                double &epair, double &v2) {
+                                                const double4 &v_bath, const double3 &xi_next, double c2_next,
+                                                const ForceOut &o, const PotConst &pc, double &epair, double &v2) {
 #pragma clang fp contract(off)
     const double ei = pc.half_eps_an * eu;
     double4 vi = v_bath;
@@ -332,7 +343,7 @@ __device__ __forceinline__ void force_atom_bath(int i, double fx, double fy, dou
     vi.y = vi.y + o.h * fy;
     vi.z = vi.z + o.h * fz;
     // this is step st->step + local + 1 of the cluster; prepare the next one
-    bath_drift(d, o.st->step + o.local + 2, i - d.off, o.mass_u, o.dt, rn, vi);
+    bath_drift_xi(d, c2_next, xi_next, o.dt, rn, vi);
     double2 *q = o.dpv + 3 * (size_t)i;
     q[0] = make_double2(rn.x, rn.y);
     q[1] = make_double2(rn.z, vi.x);
@@ -474,14 +485,26 @@ __global__ __launch_bounds__(64 * W) void k_row_force(RowArgs ra, const double4 
             if (o.fused) f_own = o.f[rt.i0 + tid];
         }
     }
+    // Langevin: the next step's noise does not depend on the forces; it is
+    // drawn while the staging loads are in flight
+    double3 xi_next = make_double3(0.0, 0.0, 0.0);
+    double c2_next = 0.0;
+    auto draw = [&] {
+        if (o.fused == 2 && tid < L.ni) {
+            const int64_t next = o.st->step + o.local + 2;
+            xi_next = bath_noise(o.cd[0].seed, next, rt.i0 - rt.off + tid);
+            c2_next = bath_c2(o.cd[0], next, o.mass_u);
+        }
+    };
     double *sh = reinterpret_cast<double *>(lds_row);
     if constexpr (STAGE) {
         double4 *lj = lds_row;
         sh += 4 * (size_t)rt.n;
-        stage_copy<W>(lj, src, rt.n);
+        stage_copy<W>(lj, src, rt.n, draw);
         row_loop(L, lj, rt.n, i_local, pair, 0, L.k_end);
         src = lj;
     } else {
+        draw();
         row_loop(L, src, rt.n, i_local, pair, 0, L.k_end);
     }
     unscale_force<PREC, GEN>(fx, fy, fz, eu);
@@ -492,7 +515,8 @@ __global__ __launch_bounds__(64 * W) void k_row_force(RowArgs ra, const double4 
     if (tid < L.ni) {
         const int i = rt.i0 + tid;
         if (o.fused == 2)
-            force_atom_bath(i, v[0], v[1], v[2], v[3], src[i - rt.off], v_own, o, pc, epair, v2);
+            force_atom_bath(i, v[0], v[1], v[2], v[3], src[i - rt.off], v_own, xi_next, c2_next, o, pc, epair,
+                            v2);
         else if (o.fused)
             force_atom_fused(i, v[0], v[1], v[2], v[3], src[i - rt.off], v_own, f_own, o, pc, epair, v2);
         else

@@ -178,7 +178,9 @@ class Workload:
     offsets: np.ndarray             # (n_clusters + 1,) int64
     dt: float                       # fs
     steps: int                      # steps of the full run
-    thermostat: list = field(default_factory=list)  # per cluster: None or dict(T_start, T_end, ramp_steps, tau)
+    # per cluster: None, dict(T_start, T_end, ramp_steps, tau) for Berendsen,
+    # or dict(kind="langevin", T_start, T_end, ramp_steps, gamma, seed)
+    thermostat: list = field(default_factory=list)
     rc: float = 0.0                 # cutoff radius for the cell-list variant (0 = all pairs)
     precision: str = "fp64"
 
@@ -267,6 +269,20 @@ def c5_batch(seed: int = 355900, n_clusters: int = 256, n_min: int = 147, n_max:
                     np.ascontiguousarray(np.concatenate(vel)), offsets, dt, steps, th)
 
 
+def in_langevin_bath(w: Workload, gamma: float = 10.0, seed: int = 1) -> Workload:
+    """The same clusters and temperature programme in a Langevin bath of
+    damping gamma (1/ps; the paper uses 10), cluster k keyed by seed + k."""
+    th = []
+    for k, t in enumerate(w.thermostat):
+        if t is None:
+            th.append(None)
+        else:
+            th.append(dict(kind="langevin", T_start=t["T_start"], T_end=t["T_end"],
+                           ramp_steps=t.get("ramp_steps", 0), gamma=gamma, seed=seed + k))
+    name = w.name.replace("berendsen", "langevin") if "berendsen" in w.name else w.name + "_langevin"
+    return Workload(name, w.pos, w.vel, w.offsets, w.dt, w.steps, th, w.rc, w.precision)
+
+
 def concat(workloads) -> Workload:
     """Concatenate single- or multi-cluster workloads into one batch (same dt)."""
     pos = np.concatenate([w.pos for w in workloads])
@@ -303,6 +319,10 @@ def by_name(name: str) -> Workload:
         w.precision = "mixed"
         w.name += "_mixed"
         return w
+    if name == "ni2243_langevin":
+        return in_langevin_bath(c2_cooling(), seed=2057)
+    if name == "batch256_langevin":
+        return in_langevin_bath(c5_batch(), seed=355900)
     if name == "ni50000_allpairs":
         pos = jitter(fcc_exact(50000), 0.05, np.random.default_rng(50000))
         vel = maxwell_boltzmann(pos, 1900.0, np.random.default_rng(50001))
