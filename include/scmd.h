@@ -174,8 +174,10 @@ int scmd_set_integrator(scmd_ctx *ctx, double dt_fs, int precision, int neighbou
 /* Thermostat of one cluster (cluster = -1: every cluster).  Berendsen: after
  * the second half-kick of step k (k counts completed steps of that cluster
  * since init, from 1), T_k = 2 E_kin / (ndof k_B) with ndof = 3N - 6 (1 for a
- * dimer, 0 below), target T_start + (T_end - T_start) min(k, K)/K
- * (K = ramp_steps; K <= 0 means T_end at once), lambda =
+ * dimer, 0 below), target T_start + (T_end - T_start) min(k - k0, K)/K for
+ * k >= k0, where k0 is the cluster's step count when this call was made
+ * (the ramp starts now: a programme of several legs is one call per leg;
+ * K = ramp_steps; K <= 0 means T_end at once), lambda =
  * sqrt(1 + (dt/tau)(target/T_k - 1)) (1 when T_k = 0, 0 when the radicand is
  * negative), v <- lambda v.  tau_fs > 0; temperatures >= 0.  SCMD_NVE
  * ignores the other arguments.  SCMD_LANGEVIN returns SCMD_EINVAL (its
@@ -191,8 +193,9 @@ int scmd_set_thermostat(scmd_ctx *ctx, int cluster, int kind, double T_start_K, 
  *   v = c1 v + c2 xi,  c1 = exp(-gamma dt),
  *                      c2 = sqrt((1 - c1^2) k_B T_target(s) / m);
  *   r += (dt/2) v;  F = F(r);  v += (dt/2m) F;
- * with T_target(s) = T_start + (T_end - T_start) min(s, K)/K (K =
- * ramp_steps; K <= 0: T_end).  xi is three standard normal deviates per
+ * with T_target(s) = T_start + (T_end - T_start) min(s - k0, K)/K, k0 the
+ * cluster's step count when this call was made (K = ramp_steps; K <= 0:
+ * T_end).  xi is three standard normal deviates per
  * atom: the Philox4x32-10 block (Salmon et al., SC'11) of key (seed mod 2^32,
  * seed div 2^32) and counter (atom index within its cluster, 0, s mod 2^32,
  * s div 2^32), its words w mapped to u = (w + 1/2) 2^-32 and through the

@@ -63,7 +63,7 @@ class _Params(ctypes.Structure):
 class _Thermo(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("T_start", ctypes.c_double), ("T_end", ctypes.c_double),
                 ("ramp_steps", ctypes.c_int64), ("tau", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("ramp_origin", ctypes.c_int64)]
 
 
 _lib = None
@@ -235,8 +235,8 @@ def temperature(vel, mass_u: float = NI_MASS_U, kind: int = NVE) -> float:
     return float(lib.sco_temperature_dof(len(v), _ptr(v), mass_u, lib.sco_ndof_kind(len(v), kind)))
 
 
-def target_temperature(T_start, T_end, ramp_steps, k) -> float:
-    t = _Thermo(BERENDSEN, T_start, T_end, ramp_steps, 1.0, 0.0, 0)
+def target_temperature(T_start, T_end, ramp_steps, k, ramp_origin: int = 0) -> float:
+    t = _Thermo(BERENDSEN, T_start, T_end, ramp_steps, 1.0, 0.0, 0, int(ramp_origin))
     return float(_load().sco_target_temperature(ctypes.byref(t), k))
 
 
@@ -252,6 +252,7 @@ def vv_run(pos, vel, nsteps, dt=1.0, params=None, mass_u=NI_MASS_U, thermostat=N
     Berendsen, or dict(kind="langevin", T_start, T_end, ramp_steps, gamma
     (1/ps), seed) for the Langevin bath (BAOAB; the steps of the trajectory
     are numbered step0 + 1, step0 + 2, ... for the noise and the ramp).
+    Either may carry ramp_origin, the step count at which its ramp starts.
     Returns (pos, vel, force, log) with log[k] = (E_pot, E_kin, T, T_target)
     of the state after step k.
     """
@@ -264,10 +265,12 @@ def vv_run(pos, vel, nsteps, dt=1.0, params=None, mass_u=NI_MASS_U, thermostat=N
         if thermostat.get("kind", "berendsen") == "langevin":
             th = _Thermo(LANGEVIN, float(thermostat["T_start"]), float(thermostat["T_end"]),
                          int(thermostat.get("ramp_steps", 0)), 0.0, float(thermostat["gamma"]),
-                         int(thermostat.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF)
+                         int(thermostat.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF,
+                         int(thermostat.get("ramp_origin", 0)))
         else:
             th = _Thermo(BERENDSEN, float(thermostat["T_start"]), float(thermostat["T_end"]),
-                         int(thermostat.get("ramp_steps", 0)), float(thermostat["tau"]), 0.0, 0)
+                         int(thermostat.get("ramp_steps", 0)), float(thermostat["tau"]), 0.0, 0,
+                         int(thermostat.get("ramp_origin", 0)))
     log = np.zeros((max(nsteps, 0), 4))
     p = _params(params)
     rc = _load().sco_vv_run(n, _ptr(r), _ptr(v), _ptr(f), 0 if force is None else 1, ctypes.byref(p),

@@ -228,10 +228,15 @@ double sco_temperature(int64_t n, const double *vel, double mass_u) {
     return 2.0 * sco_kinetic(n, vel, mass_u) / ((double)dof * SCO_KB_EV_PER_K);
 }
 
-/* Linear target ramp: T_s + (T_e - T_s) * min(k, K) / K (K <= 0: T_e at once). */
+/* Linear target ramp begun at step count k0 (ramp_origin):
+ * T_s + (T_e - T_s) * min(k - k0, K) / K for k >= k0, T_s before (K <= 0:
+ * T_e at once).  A temperature programme of several legs (heating, then
+ * cooling) is a sequence of ramps, each begun where the previous one ends. */
 double sco_target_temperature(const sco_thermostat *t, int64_t k) {
     if (t->ramp_steps <= 0) return t->T_end;
-    int64_t kk = k < t->ramp_steps ? k : t->ramp_steps;
+    int64_t kr = k - t->ramp_origin;
+    if (kr < 0) kr = 0;
+    int64_t kk = kr < t->ramp_steps ? kr : t->ramp_steps;
     return t->T_start + (t->T_end - t->T_start) * (double)kk / (double)t->ramp_steps;
 }
 

@@ -35,6 +35,7 @@ typedef struct {
     double tau;         /* Berendsen coupling time, fs */
     double gamma;       /* Langevin damping constant, 1/ps */
     uint64_t seed;      /* Langevin noise key */
+    int64_t ramp_origin; /* step count at which the ramp starts */
 } sco_thermostat;
 
 double sco_ke_conversion(void);

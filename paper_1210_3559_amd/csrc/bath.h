@@ -59,11 +59,14 @@ __device__ __forceinline__ double3 bath_noise(uint64_t seed, int64_t step, int a
     return make_double3(ra * ca, ra * sa, rb * cospi(2.0 * unit_open(w.d)));
 }
 
-// Target temperature of the ramp at step index k (both thermostats).
+// Target temperature of the ramp at step index k (both thermostats); the
+// ramp starts at step count d.ramp_origin and holds T_start before it.
 __device__ __forceinline__ double ramp_target(const ClusterDesc &d, int64_t k) {
 #pragma clang fp contract(off)
     if (d.ramp <= 0) return d.T_end;
-    const int64_t kk = k < d.ramp ? k : d.ramp;
+    int64_t kr = k - d.ramp_origin;
+    if (kr < 0) kr = 0;
+    const int64_t kk = kr < d.ramp ? kr : d.ramp;
     return d.T_start + (d.T_end - d.T_start) * (double)kk / (double)d.ramp;
 }
 

@@ -54,6 +54,7 @@ struct ClusterDesc {
     double gamma;       // Langevin damping constant, 1/ps
     double bath_c1;     // Langevin exp(-gamma dt) (set by the host for the current dt)
     uint64_t seed;      // Langevin noise key
+    int64_t ramp_origin;  // step count at which the temperature ramp starts
 };
 
 // Mutable per-cluster state (device).

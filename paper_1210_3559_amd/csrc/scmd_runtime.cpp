@@ -1162,6 +1162,7 @@ int scmd_set_thermostat(scmd_ctx *ctx, int cluster, int kind, double T_start_K, 
             d.T_end = T_end_K;
             d.ramp = ramp_steps;
             d.tau = tau_fs;
+            d.ramp_origin = ctx->step;
         }
     }
     return apply_thermostat_change(ctx);
@@ -1184,6 +1185,7 @@ int scmd_set_langevin(scmd_ctx *ctx, int cluster, double T_start_K, double T_end
         d.ramp = ramp_steps;
         d.gamma = gamma_per_ps;
         d.seed = seed;
+        d.ramp_origin = ctx->step;
     }
     return apply_thermostat_change(ctx);
 }
@@ -1498,6 +1500,7 @@ int scmd_set_state(scmd_ctx *ctx, const void *buf, size_t bytes) {
             ctx->cdesc[k].ramp = cd[k].ramp;
             ctx->cdesc[k].gamma = cd[k].gamma;
             ctx->cdesc[k].seed = cd[k].seed;
+            ctx->cdesc[k].ramp_origin = cd[k].ramp_origin;
         }
         p += ctx->nclusters * sizeof(ClusterDesc);
         HIP_TRY(ctx, hipMemcpy(ctx->d_state.p, p, ctx->nclusters * sizeof(ClusterState), hipMemcpyHostToDevice));

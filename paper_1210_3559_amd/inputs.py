@@ -283,6 +283,31 @@ def in_langevin_bath(w: Workload, gamma: float = 10.0, seed: int = 1) -> Workloa
     return Workload(name, w.pos, w.vel, w.offsets, w.dt, w.steps, th, w.rc, w.precision)
 
 
+def heating_cooling_legs(T_low: float = 400.0, T_high: float = 1400.0, rate_K_per_ps: float = 1.0,
+                         dt: float = 1.0):
+    """Temperature programme of a heating-cooling cycle at a constant rate:
+    [(T_start, T_end, steps)] for the heating and the cooling leg."""
+    steps = int(round(abs(T_high - T_low) / rate_K_per_ps * 1000.0 / dt))
+    return [(T_low, T_high, steps), (T_high, T_low, steps)]
+
+
+def ni2057_cycle(replicas: int = 1, seed: int = 2057, T_low: float = 400.0, gamma: float = 10.0,
+                 dt: float = 1.0) -> Workload:
+    """Mackay Ni2057 icosahedron (8 shells, 2.49 A) with Maxwell-Boltzmann
+    velocities at T_low, in a Langevin bath at T_low; `replicas` independent
+    copies (own velocities and bath seeds) form a batch.  The cycle's legs
+    come from heating_cooling_legs."""
+    base = mackay_icosahedron(8, 2.49)
+    pos, vel, th = [], [], []
+    for k in range(replicas):
+        pos.append(base)
+        vel.append(maxwell_boltzmann(base, T_low, np.random.default_rng(seed + 1 + k)))
+        th.append(dict(kind="langevin", T_start=T_low, T_end=T_low, ramp_steps=0, gamma=gamma, seed=seed + k))
+    offsets = np.arange(replicas + 1, dtype=np.int64) * len(base)
+    return Workload(f"ni2057_icosahedron_cycle_x{replicas}", np.ascontiguousarray(np.concatenate(pos)),
+                    np.ascontiguousarray(np.concatenate(vel)), offsets, dt, 0, th)
+
+
 def concat(workloads) -> Workload:
     """Concatenate single- or multi-cluster workloads into one batch (same dt)."""
     pos = np.concatenate([w.pos for w in workloads])
@@ -323,6 +348,12 @@ def by_name(name: str) -> Workload:
         return in_langevin_bath(c2_cooling(), seed=2057)
     if name == "batch256_langevin":
         return in_langevin_bath(c5_batch(), seed=355900)
+    if name == "ni2057_cycle":
+        w = ni2057_cycle()
+        lo, hi, n = heating_cooling_legs()[0]
+        w.thermostat = [dict(t, T_start=lo, T_end=hi, ramp_steps=n) for t in w.thermostat]
+        w.steps = n
+        return w
     if name == "ni50000_allpairs":
         pos = jitter(fcc_exact(50000), 0.05, np.random.default_rng(50000))
         vel = maxwell_boltzmann(pos, 1900.0, np.random.default_rng(50001))

@@ -208,3 +208,33 @@ def test_langevin_argument_errors():
         scmd.scmd_set_langevin(ctx, -1, 300.0, 300.0, 0, 0.0, seed=2 ** 64 - 1)
     finally:
         scmd.scmd_destroy(ctx)
+
+
+@pytest.mark.parametrize("kind", ["langevin", "berendsen"])
+def test_two_leg_temperature_programme(kind):
+    # heating then cooling: the second leg's ramp starts at the step count
+    # where it is set (ramp_origin), as a programme of legs needs
+    w = inputs.c1_icosahedron()
+    if kind == "langevin":
+        leg1 = _bath(900.0, seed=4, T_start=500.0, ramp=30)
+        leg2 = _bath(300.0, seed=4, T_start=900.0, ramp=40)
+    else:
+        leg1 = dict(T_start=500.0, T_end=900.0, ramp_steps=30, tau=40.0)
+        leg2 = dict(T_start=900.0, T_end=300.0, ramp_steps=40, tau=40.0)
+    r1, v1, f1, l1 = oracle.vv_run(w.pos, w.vel, 37, dt=1.0, thermostat=leg1, nthreads=NT)
+    r2, v2, _, l2 = oracle.vv_run(r1, v1, 50, dt=1.0, thermostat=dict(leg2, ramp_origin=37), step0=37, force=f1,
+                                  nthreads=NT)
+    assert l2[0, 3] < 900.0 and l2[39, 3] == 300.0 and l1[29, 3] == 900.0
+    print(f"[langevin] two-leg programme {kind}", flush=True)
+    with scmd.Simulation(w.offsets, w.pos, w.vel, dt=1.0, thermostats=[leg1]) as sim:
+        sim.set_sampling(1, capacity=128)
+        sim.step(37)
+        sim.set_thermostat(0, leg2)
+        sim.step(18)
+        sim.step(32)
+        r, v = sim.positions(), sim.velocities()
+        smp, recorded = sim.samples(0)
+    assert recorded == 87
+    np.testing.assert_array_equal(smp[:, 4], np.concatenate([l1[:, 3], l2[:, 3]]))
+    assert np.abs(r - r2).max() < 1e-9
+    assert np.abs(v - v2).max() < 1e-10

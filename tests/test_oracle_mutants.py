@@ -37,6 +37,7 @@ MUTANTS = {
     "philox_word_order": ("const uint32_t n1 = (uint32_t)p1;", "const uint32_t n1 = (uint32_t)p0;"),
     "box_muller_pair": ("out[1] = ra * sin(two_pi * u[1]);", "out[1] = ra * cos(two_pi * u[1]);"),
     "noise_ignores_step": ("(uint32_t)atom, 0u, (uint32_t)st,", "(uint32_t)atom, 0u, (uint32_t)atom,"),
+    "ramp_origin_sign": ("int64_t kr = k - t->ramp_origin;", "int64_t kr = k + t->ramp_origin;"),
     "ramp_index": ("t->T_start + (t->T_end - t->T_start) * (double)kk", "t->T_end + (t->T_start - t->T_end) * (double)kk"),
 }
 

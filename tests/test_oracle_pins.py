@@ -369,6 +369,13 @@ def test_berendsen_ramp_target(oracle_mod):
     assert oracle_mod.target_temperature(2000.0, 800.0, 200000, 100000) == pytest.approx(1400.0, rel=1e-15)
     assert oracle_mod.target_temperature(2000.0, 800.0, 200000, 10 ** 7) == 800.0
     assert oracle_mod.target_temperature(2000.0, 800.0, 0, 5) == 800.0
+    # a ramp begun at step 3000 (the second leg of a programme): flat before,
+    # the midpoint 1e5 steps later, the end value after
+    assert oracle_mod.target_temperature(2000.0, 800.0, 200000, 1000, ramp_origin=3000) == 2000.0
+    assert oracle_mod.target_temperature(2000.0, 800.0, 200000, 3000, ramp_origin=3000) == 2000.0
+    assert oracle_mod.target_temperature(2000.0, 800.0, 200000, 103000, ramp_origin=3000) == pytest.approx(
+        1400.0, rel=1e-15)
+    assert oracle_mod.target_temperature(2000.0, 800.0, 200000, 203000, ramp_origin=3000) == 800.0
 
 
 def test_subset_forces_equal_full_forces(oracle_mod):
