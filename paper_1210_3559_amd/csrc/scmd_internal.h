@@ -183,34 +183,37 @@ struct RowLaunch {
     int uni_off, uni_n, uni_ni;  // uni_ni = 0: use the tables
 };
 constexpr int kRowStageMax = 4096;  // clusters up to this size are staged in LDS (128 KiB)
-// Drift folded into the row density sweep of a single staged cluster: every
-// workgroup drifts the whole cluster while staging it (r + dt (lambda v +
-// h F)); mode 2 first finishes the previous step's thermostat factor from its
-// v^2 tile sums (the finalize's order, so the same bits) and workgroup 0
-// stores it in st->lambda for the force sweep, whose epilogue (fused = 1)
-// applies lambda and the first half-kick and stores the positions.
+// Drift folded into the row density sweep of staged clusters (a single
+// cluster or a batch): every workgroup drifts its whole cluster while staging
+// it (r + dt (lambda v + h F)); mode 2 first finishes the previous step's
+// thermostat factor from the cluster's v^2 tile sums (the finalize's order,
+// so the same bits) and the cluster's first tile stores it in st[c].lambda
+// for the force sweep, whose epilogue (fused) applies lambda and the first
+// half-kick and stores the positions.  Clusters in a Langevin bath have
+// their drifted (r, v) stored by the previous force epilogue (or by
+// launch_bath_prep before the run's first step) and are only staged.
 struct RowDrift {
-    int mode;   // 0: positions as they are; 1: drift with st->lambda; 2: new lambda, then drift;
-                // 3: Langevin, the stored (r, v) are already drifted
-    int local;  // mode 2: steps completed in this run (ramp index st->step + local)
+    int mode;   // 0: positions as they are; 1: drift with st[c].lambda; 2: new lambda, then drift
+    int local;  // steps completed in this run before this one (ramp index st[c].step + local)
+    int bath;   // clusters in a Langevin bath: 0 none, 1 all, 2 some (the kernel reads each one's kind)
 };
 // The drifted position is evaluated as p + (dt lambda) v with p = r + (dt h) F:
 // mode 1 forms p from r and F, mode 2 reads p and v as stored by the previous
 // fused force epilogue (48 bytes per atom), with the same rounding.
 hipError_t launch_row_density(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, const RowDrift &dr,
                               const PotConst &pc, int precision, hipStream_t s);
-// fused = 1: Berendsen/NVE epilogue (lambda, both half-kicks, next drift
-// inputs); fused = 2: Langevin epilogue (second half-kick of the stored
+// fused: per cluster, the Berendsen/NVE epilogue (lambda, both half-kicks,
+// next drift inputs) or the Langevin one (second half-kick of the stored
 // post-bath velocity, then the first half-kick and the A, O, A of the next
-// step, whose drifted (r, v) are stored for mode 3).  local = steps of this
-// run completed before this one (the step is st->step + local + 1).
+// step, whose drifted (r, v) are stored).  local = steps of this run
+// completed before this one (the step is st[c].step + local + 1).
 hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, int fused, int local,
-                            const PotConst &pc, int precision, hipStream_t s);
-// Langevin, single cluster, first step of a run: the first half-kick (after
-// the pending thermostat factor) and the A, O, A of step st->step + 1, stored
-// as the drifted (r, v) pairs that mode 3 reads.
-hipError_t launch_bath_prep(const StepArgs &a, const double4 *rp, const double4 *v, const double4 *f,
-                            double2 *dpv, int natoms, hipStream_t s);
+                            int bath, const PotConst &pc, int precision, hipStream_t s);
+// Clusters in a Langevin bath, first step of a run on the fused row path:
+// the first half-kick (after the pending thermostat factor) and the A, O, A
+// of step st[c].step + 1, stored as the drifted (r, v) pairs.
+hipError_t launch_bath_prep(const StepArgs &a, const int32_t *atom_cluster, const double4 *rp, const double4 *v,
+                            const double4 *f, double2 *dpv, int natoms, hipStream_t s);
 
 // Per-cluster energies, temperature and thermostat factor from the tile sums;
 // step_add = steps completed since the cluster step counter was last stored

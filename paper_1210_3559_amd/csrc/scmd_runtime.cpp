@@ -161,6 +161,10 @@ int fail(scmd_ctx *c, int code, const std::string &msg) {
         return fail(ctx, SCMD_EDEVICE, "internal error");        \
     }
 
+// Batches of staged clusters (all <= kRowStageMax atoms) up to this many
+// unordered pairs per step run on the row sweeps by default.
+constexpr double kRowBatchPairs = 2.5e7;
+
 int64_t ndof_of(int64_t n) {
     if (n >= 3) return 3 * n - 6;
     if (n == 2) return 1;
@@ -390,7 +394,16 @@ int build_row_plan(scmd_ctx *c, int target, std::vector<ITile> *tiles_out) {
         ClusterDesc &d = c->cdesc[k];
         const int off = (int)c->offsets[k];
         const int n = (int)(c->offsets[k + 1] - c->offsets[k]);
-        const int ni = n > 0 ? (int)std::min<double>(ni_cap, std::max(1.0, std::ceil(wstar / n))) : 1;
+        int ni = n > 0 ? (int)std::min<double>(ni_cap, std::max(1.0, std::ceil(wstar / n))) : 1;
+        // each atom of a tile gets floor(groups / ni) of the 8-lane groups;
+        // when that leaves more than a tenth of the groups idle, take the
+        // largest power of two <= ni instead (it divides the group count)
+        const int groups = 8 * c->row_waves;
+        if (ni * (groups / ni) < groups - groups / 10) {
+            int p2 = 1;
+            while (2 * p2 <= ni) p2 *= 2;
+            ni = p2;
+        }
         d.off = off;
         d.n = n;
         d.tile0 = (int)tiles.size();
@@ -456,7 +469,14 @@ int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
         // row sweeps: single clusters up to 4096 atoms, unless a one-sided
         // launch shape was given
         const bool shape_given = c->tuning.ipt > 0 || c->tuning.waves_i > 0 || c->tuning.waves_j > 0;
-        const bool row_default = !batch && nmax <= 4096 && !shape_given;
+        double upairs = 0.0;  // unordered pairs per step
+        for (int k = 0; k < c->nclusters; ++k) {
+            const double n = (double)(c->offsets[k + 1] - c->offsets[k]);
+            upairs += 0.5 * n * (n - 1.0);
+        }
+        // row sweeps evaluate every ordered pair but finish a step in two
+        // launches; the symmetric sweeps need enough work to fill the chip
+        const bool row_default = nmax <= 4096 && !shape_given && (!batch || upairs <= kRowBatchPairs);
         if (c->neighbour == SCMD_ALLPAIRS && (c->tuning.pairs == 3 || (c->tuning.pairs == 0 && row_default))) {
             c->sym = false;
             c->row = true;
@@ -465,8 +485,14 @@ int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
         }
         c->sym = allowed && (c->tuning.pairs == 2 || (c->tuning.pairs == 0 && (batch || nmax > 4096)));
         if (c->sym) {
-            int ipt = (batch || nmax > 32768) ? 4 : 2;
-            int target = (batch || nmax > 32768) ? 8192 : 2048;
+            int ipt = nmax > 32768 ? 4 : 2;
+            int target = nmax > 32768 ? 8192 : 2048;
+            if (batch) {
+                // about 32k pairs per work item, 512 to 8192 items
+                ipt = upairs >= 2e8 ? 4 : 2;
+                target = 512;
+                while (target < 8192 && target * 32768.0 * 1.5 < upairs) target *= 2;
+            }
             if (c->tuning.ipt == 2 || c->tuning.ipt == 4 || c->tuning.ipt == 8) ipt = c->tuning.ipt;
             if (c->tuning.target_items > 0) target = c->tuning.target_items;
             c->sym_ipt = ipt;
@@ -638,8 +664,13 @@ hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int adv
     } else if (c->row) {
         const RowLaunch R{c->d_tiles.p, c->d_order.p, c->d_cdesc.p, c->ntiles, c->row_waves, c->row_nmax,
                           c->row_uni_off, c->row_uni_n, c->row_uni_ni};
-        e = force ? launch_row_force(R, B, A, fused, local, c->pc, c->precision, s)
-                  : launch_row_density(R, B, A, RowDrift{drift_mode, local}, c->pc, c->precision, s);
+        // which clusters are in a Langevin bath (fixed while a graph exists:
+        // thermostat changes drop it)
+        int nb = 0;
+        for (const ClusterDesc &d : c->cdesc) nb += d.kind == SCMD_LANGEVIN;
+        const int bath = nb == 0 ? 0 : (nb == c->nclusters ? 1 : 2);
+        e = force ? launch_row_force(R, B, A, fused, local, bath, c->pc, c->precision, s)
+                  : launch_row_density(R, B, A, RowDrift{drift_mode, local, bath}, c->pc, c->precision, s);
     } else if (c->neighbour == SCMD_CELLLIST) {
         e = force ? cell_list_force(c->cells, B, A, c->d_tiles.p, c->ntiles, c->tile, c->pc, c->precision, s)
                   : cell_list_density(c->cells, B, c->d_tiles.p, c->ntiles, c->tile, c->pc, c->precision, s);
@@ -702,24 +733,25 @@ hipError_t enqueue_forces(scmd_ctx *c, hipStream_t s, bool capturing, int advanc
 hipError_t enqueue_run(scmd_ctx *c, hipStream_t s, bool capturing, int64_t nsteps) {
     hipError_t e;
     const StepArgs A = step_args(c, 1);
-    if (c->row && c->nclusters == 1 && c->row_nmax <= kRowStageMax && c->natoms > 0) {
-        // two launches per step: the density sweep drifts the staged cluster
-        // (after finishing the previous step's thermostat factor), the force
-        // sweep's epilogue kicks and stores the positions.  In a Langevin
-        // bath the force epilogue also runs the next step's bath moves and
-        // stores the drifted positions (a per-atom kernel does so before the
-        // first step of the run).
-        const bool bath = c->cdesc[0].kind == SCMD_LANGEVIN;
+    if (c->row && c->row_nmax <= kRowStageMax && c->natoms > 0) {
+        // two launches per step: the density sweep drifts each staged
+        // cluster (after finishing the previous step's thermostat factor),
+        // the force sweep's epilogue kicks and stores the positions.  For a
+        // cluster in a Langevin bath the force epilogue also runs the next
+        // step's bath moves and stores the drifted positions (a per-atom
+        // kernel does so before the first step of the run).
+        bool bath = false;
+        for (const ClusterDesc &d : c->cdesc) bath = bath || d.kind == SCMD_LANGEVIN;
         for (int64_t k = 0; k < nsteps; ++k) {
             // the sampled step is the last one without the pair energy
             if (capturing) c->capture_sample = (k == std::max<int64_t>(0, nsteps - 2));
             const int en = k == nsteps - 1;
             if (bath && k == 0 &&
-                (e = launch_bath_prep(A, c->rp.p, c->v.p, c->f.p, c->dpv.p, c->natoms, s)) != hipSuccess)
+                (e = launch_bath_prep(A, c->atom_cluster.p, c->rp.p, c->v.p, c->f.p, c->dpv.p, c->natoms, s)) !=
+                    hipSuccess)
                 return e;
-            const int mode = bath ? 3 : (k == 0 ? 1 : 2);
-            if ((e = sweep(c, false, s, capturing, 1, 1, mode, (int)k)) != hipSuccess) return e;
-            if ((e = sweep(c, true, s, capturing, 1, en, 0, (int)k, bath ? 2 : 1)) != hipSuccess) return e;
+            if ((e = sweep(c, false, s, capturing, 1, 1, k == 0 ? 1 : 2, (int)k)) != hipSuccess) return e;
+            if ((e = sweep(c, true, s, capturing, 1, en, 0, (int)k, 1)) != hipSuccess) return e;
         }
         c->capture_sample = false;
         if (nsteps > 0) return launch_finalize(A, c->d_tile_sums.p, c->nclusters, (int)nsteps, s);

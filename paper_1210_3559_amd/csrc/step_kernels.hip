@@ -53,20 +53,24 @@ __global__ __launch_bounds__(256) void k_drift(const int32_t *__restrict__ atom_
     rp[i] = ri;
 }
 
-// Langevin, single cluster: the drifted (r, v) of the first step of a run,
-// stored as the pairs (x, y), (z, vx), (vy, vz) for the row density sweep.
-__global__ __launch_bounds__(256) void k_bath_prep(const ClusterDesc *__restrict__ cd,
+// Atoms of clusters in a Langevin bath, before the first step of a run on
+// the fused row path: the drifted (r, v) of that step, stored as the pairs
+// (x, y), (z, vx), (vy, vz) that the row density sweep reads.
+__global__ __launch_bounds__(256) void k_bath_prep(const int32_t *__restrict__ atom_cluster,
+                                                   const ClusterDesc *__restrict__ cd,
                                                    const ClusterState *__restrict__ st,
                                                    const double4 *__restrict__ rp, const double4 *__restrict__ v,
                                                    const double4 *__restrict__ f, double2 *__restrict__ dpv,
                                                    int natoms, double mass_u, double dt, double h) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= natoms) return;
-    const ClusterDesc &d = cd[0];
+    const int c = atom_cluster[i];
+    const ClusterDesc &d = cd[c];
+    if (d.kind != SCMD_LANGEVIN) return;
     double4 vi = v[i];
     const double4 fi = f[i];
     double4 ri = rp[i];
-    drift_atom(d, st[0].step + 1, i - d.off, st[0].lambda, mass_u, dt, h, ri, vi, fi);
+    drift_atom(d, st[c].step + 1, i - d.off, st[c].lambda, mass_u, dt, h, ri, vi, fi);
     double2 *o = dpv + 3 * (size_t)i;
     o[0] = make_double2(ri.x, ri.y);
     o[1] = make_double2(ri.z, vi.x);
@@ -133,12 +137,12 @@ hipError_t launch_drift(const int32_t *atom_cluster, const ClusterDesc *cd, cons
     return hipGetLastError();
 }
 
-hipError_t launch_bath_prep(const StepArgs &a, const double4 *rp, const double4 *v, const double4 *f,
-                            double2 *dpv, int natoms, hipStream_t s) {
+hipError_t launch_bath_prep(const StepArgs &a, const int32_t *atom_cluster, const double4 *rp, const double4 *v,
+                            const double4 *f, double2 *dpv, int natoms, hipStream_t s) {
     if (natoms <= 0) return hipSuccess;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_bath_prep, dim3((natoms + 255) / 256), dim3(256), 0, s, a.cd, a.st, rp, v, f, dpv, natoms,
-                       a.mass_u, a.dt, a.h);
+    hipLaunchKernelGGL(k_bath_prep, dim3((natoms + 255) / 256), dim3(256), 0, s, atom_cluster, a.cd, a.st, rp, v, f,
+                       dpv, natoms, a.mass_u, a.dt, a.h);
     return hipGetLastError();
 }
 

@@ -287,6 +287,7 @@ struct ForceOut {
     const ClusterDesc *cd;
     int local;
     double dt, mass_u;
+    int bath;  // clusters in a Langevin bath: 0 none, 1 all, 2 some (read per cluster)
 };
 
 struct FinalizeArgs {

@@ -139,6 +139,8 @@ __device__ __forceinline__ double wave_sum(double x) {
 // runs (no table loads), else from the tables in launch order.
 struct RowTile {
     int tix, i0, ni, off, n;
+    int c;       // cluster
+    bool first;  // the cluster's first tile (writes its per-cluster results)
 };
 
 struct RowArgs {
@@ -156,6 +158,8 @@ __device__ __forceinline__ RowTile row_tile(const RowArgs &a) {
         r.n = a.uni_n;
         r.i0 = a.uni_off + r.tix * a.uni_ni;
         r.ni = min(a.uni_ni, a.uni_n - r.tix * a.uni_ni);
+        r.c = 0;
+        r.first = r.tix == 0;
     } else {
         r.tix = a.order[blockIdx.x];
         const ITile t = a.tiles[r.tix];
@@ -164,6 +168,8 @@ __device__ __forceinline__ RowTile row_tile(const RowArgs &a) {
         r.ni = t.ni;
         r.off = d.off;
         r.n = d.n;
+        r.c = t.c;
+        r.first = r.tix == d.tile0;
     }
     return r;
 }
@@ -249,6 +255,7 @@ __device__ __forceinline__ void stage_copy(double4 *lj, const double4 *__restric
 // Drift arguments of the density sweep (see RowDrift).
 struct RowDriftArgs {
     int mode, local;
+    int bath;  // clusters in a Langevin bath: 0 none, 1 all, 2 some (read per cluster)
     const double4 *v, *f;
     const double2 *dpv;
     ClusterState *st;
@@ -290,11 +297,10 @@ __device__ __forceinline__ double4 drifted(const PV &q, double dtl) {
 // force (as in the drift kernel), then the second half-kick with the new one;
 // the drifted position r (x, y, z of the density output) is stored.
 __device__ __forceinline__ void force_atom_fused(int i, double fx, double fy, double fz, double eu, const double4 &r,
-                                                 const double4 &v_old, const double4 &f_old, const ForceOut &o,
-                                                 const PotConst &pc, double &epair, double &v2) {
+                                                 const double4 &v_old, const double4 &f_old, double lam,
+                                                 const ForceOut &o, const PotConst &pc, double &epair, double &v2) {
 #pragma clang fp contract(off)
     const double ei = pc.half_eps_an * eu;
-    const double lam = o.st->lambda;
     const double4 fo = f_old;
     double4 vi = v_old;
     vi.x = lam * vi.x;
@@ -318,14 +324,15 @@ __device__ __forceinline__ void force_atom_fused(int i, double fx, double fy, do
     v2 += vi.x * vi.x + vi.y * vi.y + vi.z * vi.z;
 }
 
-// Langevin epilogue (fused = 2): the stored post-bath velocity gets the
-// second half-kick; then the first half-kick of the next step with the same
-// force and that step's A, O, A (bath.h), whose drifted (r, v) are stored for
-// the next density sweep (mode 3).  The order of operations is the same as in
-// the drift kernel.
+// Langevin epilogue (a cluster in a bath): the stored post-bath velocity gets
+// the second half-kick; then the first half-kick of the next step with the
+// same force and that step's A, O, A (bath.h), whose drifted (r, v) are
+// stored for the next density sweep.  The order of operations is the same as
+// in the drift kernel.
 __device__ __forceinline__ void force_atom_bath(int i, double fx, double fy, double fz, double eu, const double4 &r,
                                                 const double4 &v_bath, const double3 &xi_next, double c2_next,
-                                                const ForceOut &o, const PotConst &pc, double &epair, double &v2) {
+                                                const ClusterDesc &d, const ForceOut &o, const PotConst &pc,
+                                                double &epair, double &v2) {
 #pragma clang fp contract(off)
     const double ei = pc.half_eps_an * eu;
     double4 vi = v_bath;
@@ -337,7 +344,6 @@ __device__ __forceinline__ void force_atom_bath(int i, double fx, double fy, dou
     o.rp[i] = make_double4(r.x, r.y, r.z, 0.0);
     epair += ei;
     v2 += vi.x * vi.x + vi.y * vi.y + vi.z * vi.z;
-    const ClusterDesc &d = o.cd[0];
     double4 rn = make_double4(r.x, r.y, r.z, 0.0);
     vi.x = vi.x + o.h * fx;
     vi.y = vi.y + o.h * fy;
@@ -377,15 +383,18 @@ __global__ __launch_bounds__(64 * W) void k_row_density(RowArgs ra, DensityOut o
             qi = src[i_local];
             stage_copy<W>(lj, src, rt.n);
         } else {
-            // single cluster: drift while staging.  The loads of the own atom
-            // and of the first batch are issued before the thermostat factor
-            // is known; the factor's tile-sum loads overlap them.
-            // the own atom and the first four atoms of this thread are loaded
-            // before the thermostat factor is known (named registers, see
-            // stage_copy); mode 2 reads the stored (p, v), mode 1 forms p
+            // drift while staging.  The own atom and the first four atoms of
+            // this thread are loaded before the thermostat factor is known
+            // (named registers, see stage_copy), so the factor's tile-sum
+            // loads overlap them; mode 2 reads the stored (p, v), mode 1
+            // forms p.  A cluster in a Langevin bath has its drifted (r, v)
+            // stored already (by the previous force epilogue, or before the
+            // run's first step): it takes p + 0 v = p.
+            ClusterState *sc = da.st + rt.c;
+            const bool bath = da.bath == 1 || (da.bath == 2 && da.cd[rt.c].kind == SCMD_LANGEVIN);
             const double4 *gv = da.v + rt.off, *gf = da.f + rt.off;
             const double2 *gd = da.dpv + 3 * (size_t)rt.off;
-            const bool stored = da.mode >= 2;
+            const bool stored = da.mode == 2 || bath;
             auto load = [&](int a) { return stored ? pv_load(gd, a) : pv_from_rvf(src, gv, gf, a, da.dth); };
             const PV own = load(i_local);
             constexpr int T = 64 * W;
@@ -397,19 +406,20 @@ __global__ __launch_bounds__(64 * W) void k_row_density(RowArgs ra, DensityOut o
             if (a3 < rt.n) t3 = load(a3);
             __shared__ double sh_tot[12];
             double lam;
-            if (da.mode == 2) {
+            if (bath) {
+                lam = 0.0;
+            } else if (da.mode == 2) {
                 // finish the previous step's thermostat factor (finalize order)
-                const ClusterDesc d = da.cd[0];
+                const ClusterDesc d = da.cd[rt.c];
                 double e0, e1, v2;
                 cluster_totals<true>(d, da.tile_sums, sh_tot, e0, e1, v2);
                 const KinT kt = kinetic_temperature(d, da.mass_u, v2);
                 double tt;
-                lam = thermostat_lambda(d, da.dt, kt.T, da.st->step + da.local, &tt);
-                if (blockIdx.x == 0 && tid == 0) da.st->lambda = lam;
+                lam = thermostat_lambda(d, da.dt, kt.T, sc->step + da.local, &tt);
+                if (rt.first && tid == 0) sc->lambda = lam;
             } else {
-                lam = da.mode == 3 ? 0.0 : da.st->lambda;
+                lam = sc->lambda;
             }
-            // mode 3 stores drifted positions: p + 0 v = p
             const double dtl = da.dt * lam;
             qi = drifted(own, dtl);
             if (a0 < rt.n) lj[a0] = drifted(t0, dtl);
@@ -450,7 +460,9 @@ __global__ __launch_bounds__(64 * W) void k_row_density(RowArgs ra, DensityOut o
 // Force sweep
 // ---------------------------------------------------------------------------
 // EN: accumulate the pair energy (otherwise the energy sums are zero).
-template <int W, int PREC, bool GEN, bool STAGE, bool EN>
+// BATH: some cluster of the launch is in a Langevin bath (the bath epilogue
+// and its noise draw are compiled only then).
+template <int W, int PREC, bool GEN, bool STAGE, bool EN, bool BATH>
 __global__ __launch_bounds__(64 * W) void k_row_force(RowArgs ra, const double4 *__restrict__ xp, ForceOut o,
                                                       PotConst pc) {
     extern __shared__ double4 lds_row[];
@@ -474,8 +486,9 @@ __global__ __launch_bounds__(64 * W) void k_row_force(RowArgs ra, const double4 
     };
     // the epilogue's own-atom loads are issued now, off the critical path
     double4 v_own = make_double4(0, 0, 0, 0), f_own = make_double4(0, 0, 0, 0);
+    const bool bath = BATH && o.fused && (o.bath == 1 || (o.bath == 2 && o.cd[rt.c].kind == SCMD_LANGEVIN));
     if (tid < L.ni) {
-        if (o.fused == 2) {
+        if (bath) {
             // Langevin: the post-bath velocity stored with the drifted position
             const double2 *q = o.dpv + 3 * (size_t)(rt.i0 + tid);
             const double2 q1 = q[1], q2 = q[2];
@@ -490,10 +503,10 @@ __global__ __launch_bounds__(64 * W) void k_row_force(RowArgs ra, const double4 
     double3 xi_next = make_double3(0.0, 0.0, 0.0);
     double c2_next = 0.0;
     auto draw = [&] {
-        if (o.fused == 2 && tid < L.ni) {
-            const int64_t next = o.st->step + o.local + 2;
-            xi_next = bath_noise(o.cd[0].seed, next, rt.i0 - rt.off + tid);
-            c2_next = bath_c2(o.cd[0], next, o.mass_u);
+        if (bath && tid < L.ni) {
+            const int64_t next = o.st[rt.c].step + o.local + 2;
+            xi_next = bath_noise(o.cd[rt.c].seed, next, rt.i0 - rt.off + tid);
+            c2_next = bath_c2(o.cd[rt.c], next, o.mass_u);
         }
     };
     double *sh = reinterpret_cast<double *>(lds_row);
@@ -514,11 +527,12 @@ __global__ __launch_bounds__(64 * W) void k_row_force(RowArgs ra, const double4 
     double epair = 0.0, v2 = 0.0;
     if (tid < L.ni) {
         const int i = rt.i0 + tid;
-        if (o.fused == 2)
-            force_atom_bath(i, v[0], v[1], v[2], v[3], src[i - rt.off], v_own, xi_next, c2_next, o, pc, epair,
-                            v2);
+        if (bath)
+            force_atom_bath(i, v[0], v[1], v[2], v[3], src[i - rt.off], v_own, xi_next, c2_next, o.cd[rt.c], o, pc,
+                            epair, v2);
         else if (o.fused)
-            force_atom_fused(i, v[0], v[1], v[2], v[3], src[i - rt.off], v_own, f_own, o, pc, epair, v2);
+            force_atom_fused(i, v[0], v[1], v[2], v[3], src[i - rt.off], v_own, f_own, o.st[rt.c].lambda, o, pc,
+                             epair, v2);
         else
             force_atom_v(i, v[0], v[1], v[2], v[3], v_own, o, pc, epair, v2);
     }
@@ -548,7 +562,11 @@ hipError_t row_launch(bool force, bool energy, const RowLaunch &L, const SweepBu
     if (force) {
         const size_t lds = row_lds_bytes<W, 4, STAGE>(L.nmax);
         // the generic-exponent kernels always accumulate the energy
-        auto kern = (energy || GEN) ? k_row_force<W, PREC, GEN, STAGE, true> : k_row_force<W, PREC, GEN, STAGE, GEN>;
+        // the bath epilogue exists only in fused (staged) launches
+        constexpr bool kB = STAGE;
+        auto kern = (energy || GEN)
+                        ? (fo.bath ? k_row_force<W, PREC, GEN, STAGE, true, kB> : k_row_force<W, PREC, GEN, STAGE, true, false>)
+                        : (fo.bath ? k_row_force<W, PREC, GEN, STAGE, GEN, kB> : k_row_force<W, PREC, GEN, STAGE, GEN, false>);
         if ((e = allow_lds(kern, lds)) != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3(L.ntiles), dim3(64 * W), lds, s, ra, (const double4 *)B.xp, fo, pc);
     } else {
@@ -582,9 +600,8 @@ hipError_t row_dispatch_w(bool force, bool energy, const RowLaunch &L, const Swe
 hipError_t row_dispatch(bool force, bool energy, const RowLaunch &L, const SweepBuffers &B, const ForceOut &fo,
                         const RowDriftArgs &da, const PotConst &pc, int precision, hipStream_t s) {
     if (L.ntiles <= 0) return hipSuccess;
-    // the drift and the fused epilogue need one staged cluster
-    const bool one_staged = L.uni_ni > 0 && L.nmax <= kRowStageMax;
-    if ((da.mode != 0 || fo.fused) && !one_staged) return hipErrorInvalidValue;
+    // the drift and the fused epilogue need staged clusters
+    if ((da.mode != 0 || fo.fused) && L.nmax > kRowStageMax) return hipErrorInvalidValue;
     (void)hipGetLastError();
     switch (L.waves) {
         case 4: return row_dispatch_w<4>(force, energy, L, B, fo, da, pc, precision, s);
@@ -599,16 +616,17 @@ hipError_t row_dispatch(bool force, bool energy, const RowLaunch &L, const Sweep
 hipError_t launch_row_density(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, const RowDrift &dr,
                               const PotConst &pc, int precision, hipStream_t s) {
     const ForceOut fo{};
-    const RowDriftArgs da{dr.mode, dr.local, B.v, B.f, B.dpv, a.st, B.tile_sums, a.cd, a.mass_u, a.dt, a.h, a.dt * a.h};
+    const RowDriftArgs da{dr.mode, dr.local, dr.bath, B.v, B.f, B.dpv, a.st, B.tile_sums, a.cd, a.mass_u, a.dt, a.h,
+                          a.dt * a.h};
     return row_dispatch(false, true, L, B, fo, da, pc, precision, s);
 }
 
 hipError_t launch_row_force(const RowLaunch &L, const SweepBuffers &B, const StepArgs &a, int fused, int local,
-                            const PotConst &pc, int precision, hipStream_t s) {
+                            int bath, const PotConst &pc, int precision, hipStream_t s) {
     // the fused epilogue stores the drifted positions (rp is the context's
     // writable position array; the sweeps otherwise only read it)
-    const ForceOut fo{B.f,  B.v,       B.tile_sums, a.h,  a.advance, fused,    a.st, const_cast<double4 *>(B.rp),
-                      B.dpv, a.dt * a.h, a.cd,       local, a.dt,      a.mass_u};
+    const ForceOut fo{B.f,  B.v,       B.tile_sums, a.h,  a.advance, fused,    a.st,  const_cast<double4 *>(B.rp),
+                      B.dpv, a.dt * a.h, a.cd,       local, a.dt,      a.mass_u, bath};
     const RowDriftArgs da{};
     return row_dispatch(true, a.energy != 0, L, B, fo, da, pc, precision, s);
 }

@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import itertools
 import math
+import re
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -348,12 +349,18 @@ def by_name(name: str) -> Workload:
         return in_langevin_bath(c2_cooling(), seed=2057)
     if name == "batch256_langevin":
         return in_langevin_bath(c5_batch(), seed=355900)
-    if name == "ni2057_cycle":
-        w = ni2057_cycle()
+    m = re.fullmatch(r"ni2057_cycle(?:_x(\d+))?", name)
+    if m:
+        w = ni2057_cycle(int(m.group(1) or 1))
         lo, hi, n = heating_cooling_legs()[0]
         w.thermostat = [dict(t, T_start=lo, T_end=hi, ramp_steps=n) for t in w.thermostat]
         w.steps = n
         return w
+    m = re.fullmatch(r"fcc(\d+)_nve", name)
+    if m:
+        n = int(m.group(1))
+        pos = jitter(fcc_exact(n), 0.05, np.random.default_rng(n))
+        return _single(name, pos, maxwell_boltzmann(pos, 1200.0, np.random.default_rng(n + 1)), 1.0, 1000)
     if name == "ni50000_allpairs":
         pos = jitter(fcc_exact(50000), 0.05, np.random.default_rng(50000))
         vel = maxwell_boltzmann(pos, 1900.0, np.random.default_rng(50001))

@@ -520,6 +520,49 @@ def test_row_batch_parity():
         assert ens[k][0] == pytest.approx(site.sum(), rel=1e-10)
 
 
+@pytest.mark.parametrize("tuning", [None, dict(pairs=3, waves_j=4, target_items=50),
+                                    dict(pairs=3, waves_j=16, target_items=3000)])
+def test_fused_row_batch_trajectories(tuning):
+    # a batch on the fused two-launch row step: every cluster has its own
+    # thermostat factor (Berendsen ramps, NVE) or bath, finished inside the
+    # sweeps; empty and tiny clusters ride along
+    sizes = [147, 0, 1, 2, 333, 64, 1000, 5, 129]
+    rng = np.random.default_rng(91)
+    parts = [_cluster(s, seed=80 + k, amp=0.05) for k, s in enumerate(sizes)]
+    vels = [inputs.maxwell_boltzmann(p, 1300.0, rng) if len(p) >= 3 else rng.normal(0, 3e-3, (len(p), 3))
+            for p in parts]
+    ths = [dict(T_start=1300.0, T_end=700.0, ramp_steps=50, tau=60.0), None, None,
+           dict(kind="langevin", T_start=900.0, T_end=900.0, ramp_steps=0, gamma=10.0, seed=5),
+           dict(kind="langevin", T_start=500.0, T_end=1500.0, ramp_steps=40, gamma=10.0, seed=6), None,
+           dict(T_start=900.0, T_end=900.0, ramp_steps=0, tau=100.0),
+           dict(kind="langevin", T_start=300.0, T_end=300.0, ramp_steps=0, gamma=30.0, seed=7),
+           dict(T_start=2000.0, T_end=100.0, ramp_steps=10, tau=20.0)]
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    print(f"[parity] fused row batch tuning={tuning}", flush=True)
+    outs = []
+    for _ in range(2):
+        with scmd.Simulation(offsets, np.concatenate(parts), np.concatenate(vels), dt=1.0, thermostats=ths,
+                             tuning=tuning) as sim:
+            for c in (1, 31, 32, 7):
+                sim.step(c)
+            outs.append((sim.positions(), sim.velocities(), [sim.energy(k) for k in range(len(sizes))],
+                         [sim.temperature(k) for k in range(len(sizes))]))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    r, v, ens, temps = outs[0]
+    for k, p in enumerate(parts):
+        a, b = offsets[k], offsets[k + 1]
+        if b == a:
+            assert ens[k] == (0.0, 0.0, 0.0)
+            continue
+        r_ref, v_ref, _, log = oracle.vv_run(p, vels[k], 71, dt=1.0, thermostat=ths[k], nthreads=NT)
+        assert np.abs(r[a:b] - r_ref).max() < 1e-9, k
+        assert np.abs(v[a:b] - v_ref).max() < 1e-10, k
+        assert ens[k][0] == pytest.approx(log[-1, 0], rel=1e-10, abs=1e-12)
+        assert ens[k][1] == pytest.approx(log[-1, 1], rel=1e-9, abs=1e-14)
+        assert temps[k][0] == pytest.approx(log[-1, 2], rel=1e-9, abs=1e-9)
+
+
 @pytest.mark.parametrize("waves", [4, 8, 16])
 def test_row_trajectory_parity_and_determinism(waves):
     w = inputs.c2_cooling()
