@@ -1,0 +1,179 @@
+"""Solidification kinetics of overcooled nickel clusters (the paper's Sec. 3,
+"Solidification process" and "Kinetics of the solidification phase
+transition"): molten Ni2057 clusters are held in a Langevin bath below the
+melting point until they crystallise; the lifetime of the overcooled liquid
+is the time at which the total energy starts to drop abruptly, the escape
+rate is kappa = 1/<t> (Eq. (rate2)), and its temperature dependence is fitted
+with ln(kappa * 1 ps) = a - b / (k_B T (T - T0)^2) (Eq. (rate3)).
+
+    python -m paper_1210_3559_amd.kinetics --T 780 [--replicas 15]
+        [--max-ps 4000] [--out file.json]
+
+Replicas are independent clusters of one batch (own initial velocities and
+bath seeds): they are melted together at T_melt, quenched to T, and stepped
+until every one has crystallised or the time limit is reached (runs without
+a transition are censored at the limit).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import inputs, scmd
+
+K_B = 8.617333262145179e-05  # eV/K
+
+
+def running_mean(x, w: int) -> np.ndarray:
+    """Centred running mean over w samples (shorter at the ends)."""
+    x = np.asarray(x, dtype=np.float64)
+    if len(x) == 0 or w <= 1:
+        return x.copy()
+    c = np.concatenate([[0.0], np.cumsum(x)])
+    h = w // 2
+    lo = np.clip(np.arange(len(x)) - h, 0, len(x))
+    hi = np.clip(np.arange(len(x)) + h + 1, 0, len(x))
+    return (c[hi] - c[lo]) / (hi - lo)
+
+
+def transition_time(t, e, drop: float, settle: float = 10.0, ref: float = 40.0, smooth: int = 5):
+    """Time at which the energy per atom e(t) starts its abrupt drop by about
+    `drop` (eV/atom), or None if it never falls that far.
+
+    The liquid level is the median of the smoothed trace over [settle, settle
+    + ref] after the start; the drop is found where the smoothed trace first
+    falls below level - drop/2, and its start is the last earlier time at
+    which the trace was still above level - drop/5.
+    """
+    t = np.asarray(t, dtype=np.float64)
+    s = running_mean(e, smooth)
+    win = (t >= t[0] + settle) & (t <= t[0] + settle + ref)
+    if not win.any():
+        return None
+    level = float(np.median(s[win]))
+    below = np.nonzero((s < level - 0.5 * drop) & (t >= t[0] + settle))[0]
+    if len(below) == 0:
+        return None
+    k = int(below[0])
+    above = np.nonzero(s[:k] >= level - 0.2 * drop)[0]
+    return float(t[above[-1]] if len(above) else t[0])
+
+
+def escape_rate(lifetimes, censored_at=()):
+    """(kappa = 1/<t> over the observed lifetimes, as Eq. (rate2); the
+    maximum-likelihood rate of an exponential law with censored runs,
+    events / (sum of lifetimes + sum of censoring times))."""
+    t = np.asarray(lifetimes, dtype=np.float64)
+    c = np.asarray(censored_at, dtype=np.float64)
+    k_mean = 1.0 / t.mean() if len(t) else float("nan")
+    tot = t.sum() + c.sum()
+    k_mle = len(t) / tot if tot > 0 else float("nan")
+    return k_mean, k_mle
+
+
+def fit_rate3(T, kappa_per_ps, T0=None, p0=(1.2, 3.0e4, 1030.0)):
+    """Least-squares fit of ln(kappa * 1 ps) = a - b / (k_B T (T - T0)^2)
+    (kappa in 1/ps, b in eV K^2); returns (a, b, T0).  With T0 given only a
+    and b are fitted (three temperatures far below T0 do not determine it)."""
+    from scipy.optimize import curve_fit
+    T = np.asarray(T, dtype=np.float64)
+    y = np.log(np.asarray(kappa_per_ps, dtype=np.float64))
+    if T0 is not None:
+        def f2(x, a, b):
+            return a - b / (K_B * x * (x - T0) ** 2)
+
+        p, _ = curve_fit(f2, T, y, p0=p0[:2], maxfev=20000)
+        return float(p[0]), float(p[1]), float(T0)
+
+    def f(x, a, b, t0):
+        return a - b / (K_B * x * (x - t0) ** 2)
+
+    p, _ = curve_fit(f, T, y, p0=p0, maxfev=20000)
+    return tuple(float(v) for v in p)
+
+
+def run(T: float, replicas: int = 15, max_ps: float = 4000.0, T_melt: float = 1400.0, melt_ps: float = 100.0,
+        gamma: float = 10.0, seed: int = 820, dt: float = 1.0, sample_ps: float = 1.0, chunk_ps: float = 100.0,
+        drop: float = 0.03, log=sys.stderr) -> dict:
+    """Melt `replicas` Mackay Ni2057 clusters at T_melt, quench them to T and
+    step until all have crystallised or max_ps has passed."""
+    w = inputs.ni2057_cycle(replicas, seed=seed, T_low=T_melt, gamma=gamma, dt=dt)
+    n = int(w.sizes()[0])
+    every = max(1, int(round(sample_ps * 1000.0 / dt)))
+    chunk = max(every, int(round(chunk_ps * 1000.0 / dt)) // every * every)
+    melt_steps = int(round(melt_ps * 1000.0 / dt)) // every * every
+    max_steps = int(round(max_ps * 1000.0 / dt))
+    cap = (max_steps + melt_steps) // every + 8
+    t0 = time.perf_counter()
+    with scmd.Simulation(w.offsets, w.pos, w.vel, dt=dt, thermostats=w.thermostat) as sim:
+        sim.set_sampling(every, capacity=cap)
+        sim.step(melt_steps)
+        for k in range(replicas):
+            sim.set_thermostat(k, dict(w.thermostat[k], T_start=T, T_end=T, ramp_steps=0))
+        done, found = 0, [None] * replicas
+        while done < max_steps:
+            c = min(chunk, max_steps - done)
+            sim.step(c)
+            done += c
+            for k in range(replicas):
+                if found[k] is None:
+                    s, _ = sim.samples(k, cap)
+                    iso = s[s[:, 0] > melt_steps]
+                    tk = (iso[:, 0] - melt_steps) * dt * 1e-3  # ps since the quench
+                    found[k] = transition_time(tk, (iso[:, 1] + iso[:, 2]) / n, drop)
+            nf = sum(x is not None for x in found)
+            print(f"[kinetics] T={T:.0f} K: {done * dt * 1e-3:.0f} ps, {nf}/{replicas} crystallised, "
+                  f"{time.perf_counter() - t0:.1f} s", file=log, flush=True)
+            if nf == replicas:
+                break
+        traces = []
+        for k in range(replicas):
+            s, _ = sim.samples(k, cap)
+            iso = s[s[:, 0] > melt_steps]
+            traces.append(((iso[:, 0] - melt_steps) * dt * 1e-3, (iso[:, 1] + iso[:, 2]) / n, iso[:, 3]))
+    wall = time.perf_counter() - t0
+    run_ps = done * dt * 1e-3
+    life = [x for x in found if x is not None]
+    cens = [run_ps] * (replicas - len(life))
+    k_mean, k_mle = escape_rate(life, cens)
+    # latent heat: liquid level before the drop minus the solid level at the end
+    lat = []
+    for (tk, ek, _), x in zip(traces, found):
+        if x is not None and tk[-1] - x > 60.0:
+            liq = np.median(ek[(tk >= 10.0) & (tk <= max(20.0, x - 5.0))])
+            sol = np.median(ek[tk >= tk[-1] - 30.0])
+            lat.append(float(liq - sol) * n)
+    return {
+        "T_K": T, "replicas": replicas, "atoms_per_cluster": n, "gamma_per_ps": gamma, "dt_fs": dt,
+        "melt": {"T_K": T_melt, "ps": melt_steps * dt * 1e-3}, "max_ps": max_ps, "run_ps": run_ps,
+        "lifetimes_ps": [x for x in found], "n_crystallised": len(life), "mean_lifetime_ps": (
+            float(np.mean(life)) if life else None),
+        "kappa_per_ps": k_mean, "kappa_mle_per_ps": k_mle, "latent_heat_eV": (float(np.mean(lat)) if lat else None),
+        "seconds": wall, "us_per_step": 1e6 * wall / (done + melt_steps),
+        "traces": [{"t_ps": [float(v) for v in tk[::10]], "e_per_atom": [float(v) for v in ek[::10]]}
+                   for tk, ek, _ in traces],
+    }
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--T", type=float, required=True, help="bath temperature, K")
+    ap.add_argument("--replicas", type=int, default=15)
+    ap.add_argument("--max-ps", type=float, default=4000.0)
+    ap.add_argument("--seed", type=int, default=820)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    res = run(args.T, args.replicas, args.max_ps, seed=args.seed)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(res, f)
+    print(json.dumps({k: v for k, v in res.items() if k != "traces"}))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
