@@ -15,7 +15,9 @@ reversibility and Berendsen relaxation; the Langevin bath by the published
 Philox4x32-10 known-answer blocks, the normal law of its deviates, the
 reduction to velocity-Verlet at zero damping, the closed-form decay of a free
 atom in a bath at 0 K and the equipartition temperature of free atoms and of
-a cluster.  Nothing in this package is "parity unpinned".
+a cluster; the pair-distance histogram by the fcc neighbour-shell
+multiplicities, the pair count and the dimer and trimer.  Nothing in this
+package is "parity unpinned".
 
 Arrays are numpy float64 of shape (n, 3) for positions, velocities and
 forces.  Units: Angstrom, fs, eV, u, K.
@@ -90,6 +92,8 @@ def _configure(lib):
     lib.sco_philox4x32_10.restype = None
     lib.sco_gauss3.argtypes = [ctypes.c_uint64, i64, i64, vp]
     lib.sco_gauss3.restype = None
+    lib.sco_rdf.argtypes = [i64, vp, dbl, dbl, ctypes.c_int, vp, ctypes.POINTER(i64)]
+    lib.sco_rdf.restype = ctypes.c_int
     lib.sco_kinetic.argtypes = [i64, vp, dbl]
     lib.sco_kinetic.restype = dbl
     lib.sco_temperature.argtypes = [i64, vp, dbl]
@@ -281,6 +285,19 @@ def vv_run(pos, vel, nsteps, dt=1.0, params=None, mass_u=NI_MASS_U, thermostat=N
     return r, v, f, log
 
 
+def rdf_counts(pos, dr: float, nbins: int, r_select: float = 0.0):
+    """(counts (nbins,) uint64, n_ref): pair-distance histogram of the atoms
+    within r_select of the centre of mass (all atoms when r_select <= 0)
+    against every other atom; bin = floor(|r_i - r_j| / dr)."""
+    r = _pos(pos)
+    counts = np.zeros(int(nbins), dtype=np.uint64)
+    nref = ctypes.c_int64(0)
+    rc = _load().sco_rdf(len(r), _ptr(r), float(r_select), float(dr), int(nbins), _ptr(counts), ctypes.byref(nref))
+    if rc != 0:
+        raise ValueError("invalid histogram arguments")
+    return counts, int(nref.value)
+
+
 def load_variant(lib_path: str):
     """Bind the same API to another build of the oracle source (used by the
     tests that plant a mistake in a copy of the oracle and check that the
@@ -291,7 +308,7 @@ def load_variant(lib_path: str):
     g = globals()
     for name in ("max_threads", "ke_conversion", "kb", "density", "forces", "forces_subset", "energy", "site_energies", "ndof",
                  "kinetic", "temperature", "target_temperature", "berendsen_lambda", "vv_run", "philox4x32_10",
-                 "gauss3"):
+                 "gauss3", "rdf_counts"):
         fn = g[name]
         def bound(*a, _fn=fn, **k):
             global _lib

@@ -322,6 +322,43 @@ void sco_gauss3(uint64_t seed, int64_t step, int64_t atom, double out[3]) {
 }
 
 /*
+ * Pair-distance histogram behind the radial distribution function g(r) =
+ * rho(r) / rho_bar (Sec. 3, "Radial distribution function as an indicator of
+ * the phase transition", Eq. (Rdist)): the reference atoms are those closer
+ * than r_select to the centre of mass (x_c = (sum_i x_i) / n in index order;
+ * r_select <= 0 takes every atom); for each reference atom i and every other
+ * atom j, r = sqrt(dx*dx + dy*dy + dz*dz) with d = r_i - r_j, and the pair
+ * is counted in bin floor(r / dr) when that is below nbins.  counts[nbins]
+ * and *n_ref are added to (the caller clears them), so frames accumulate.
+ * Returns 0, or -1 on bad arguments.
+ */
+int sco_rdf(int64_t n, const double *pos, double r_select, double dr, int nbins, uint64_t *counts,
+            int64_t *n_ref) {
+    if (n < 0 || !(dr > 0.0) || nbins <= 0) return -1;
+    double c[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) c[d] += pos[3 * i + d];
+    if (n > 0)
+        for (int d = 0; d < 3; ++d) c[d] /= (double)n;
+    const double rs2 = r_select * r_select;
+    for (int64_t i = 0; i < n; ++i) {
+        const double ex = pos[3 * i] - c[0], ey = pos[3 * i + 1] - c[1], ez = pos[3 * i + 2] - c[2];
+        if (r_select > 0.0 && !(ex * ex + ey * ey + ez * ez < rs2)) continue;
+        *n_ref += 1;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double dx = pos[3 * i] - pos[3 * j];
+            const double dy = pos[3 * i + 1] - pos[3 * j + 1];
+            const double dz = pos[3 * i + 2] - pos[3 * j + 2];
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double b = floor(r / dr);
+            if (b < (double)nbins) counts[(int64_t)b] += 1;
+        }
+    }
+    return 0;
+}
+
+/*
  * Velocity-Verlet trajectory.  On entry pos/vel hold r(t0), v(t0) (n x 3,
  * row-major); force holds F(r(t0)) when have_force is set, else it is
  * computed first.  Each step:

@@ -60,6 +60,9 @@ double sco_temperature(int64_t n, const double *vel, double mass_u);
 double sco_target_temperature(const sco_thermostat *t, int64_t k);
 double sco_berendsen_lambda(double T, double T_target, double dt, double tau);
 
+int sco_rdf(int64_t n, const double *pos, double r_select, double dr, int nbins, uint64_t *counts,
+            int64_t *n_ref);
+
 int sco_vv_run(int64_t n, double *pos, double *vel, double *force, int have_force, const sco_params *p,
                double mass_u, double dt, int64_t nsteps, const sco_thermostat *thermo, int64_t step0,
                double *log, int nthreads);

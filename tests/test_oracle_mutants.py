@@ -11,6 +11,7 @@ import pytest
 import oracle
 import test_oracle_langevin as lpins
 import test_oracle_pins as pins
+import test_oracle_rdf as rpins
 from paper_1210_3559_amd import inputs
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "sc_oracle.c")
@@ -38,6 +39,10 @@ MUTANTS = {
     "box_muller_pair": ("out[1] = ra * sin(two_pi * u[1]);", "out[1] = ra * cos(two_pi * u[1]);"),
     "noise_ignores_step": ("(uint32_t)atom, 0u, (uint32_t)st,", "(uint32_t)atom, 0u, (uint32_t)atom,"),
     "ramp_origin_sign": ("int64_t kr = k - t->ramp_origin;", "int64_t kr = k + t->ramp_origin;"),
+    "rdf_bin_rounding": ("const double b = floor(r / dr);", "const double b = floor(r / dr + 0.5);"),
+    "rdf_self_pair": ("            if (j == i) continue;\n            const double dx = pos[3 * i] - pos[3 * j];",
+                      "            const double dx = pos[3 * i] - pos[3 * j];"),
+    "rdf_centre_not_averaged": ("for (int d = 0; d < 3; ++d) c[d] /= (double)n;", "for (int d = 0; d < 3; ++d) c[d] /= 1.0;"),
     "ramp_index": ("t->T_start + (t->T_end - t->T_start) * (double)kk", "t->T_end + (t->T_start - t->T_end) * (double)kk"),
 }
 
@@ -76,6 +81,11 @@ def _pin_calls():
         lambda o: pins.test_dimer_harmonic_period(o),
         lambda o: pins.test_berendsen_relaxes_to_target(o, ni147),
         lambda o: pins.test_time_reversibility(o, ni147),
+        lambda o: rpins.test_fcc_central_atom_shells(o),
+        lambda o: rpins.test_total_count_is_every_ordered_pair(o),
+        lambda o: rpins.test_dimer_and_trimer(o),
+        lambda o: rpins.test_mackay_selection(o),
+        lambda o: rpins.test_invariant_under_rigid_motion_and_relabelling(o),
         lambda o: lpins.test_philox_known_answers(o),
         lambda o: lpins.test_noise_is_standard_normal(o),
         lambda o: lpins.test_noise_box_muller_structure(o),
