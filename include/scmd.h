@@ -275,6 +275,23 @@ int scmd_get_density(scmd_ctx *ctx, double *out);
  * device memory dev_out, ordered on the context stream; does not wait. */
 int scmd_get_forces_device(scmd_ctx *ctx, double *dev_out);
 
+/* Pair-distance histogram behind the radial distribution function
+ * g(r) = rho(r) / rho_bar of one cluster at its current positions (Sec. 3,
+ * "Radial distribution function as an indicator of the phase transition",
+ * Eq. (Rdist)).  Reference atoms: those closer than r_select (A) to the
+ * cluster's centre of mass (every atom when r_select <= 0).  Each pair of a
+ * reference atom i and another atom j of the cluster adds 1 to bin
+ * floor(r_ij / dr) when that is below nbins, r_ij = sqrt(dx*dx + dy*dy +
+ * dz*dz) with d = r_i - r_j evaluated in IEEE double without contraction.
+ * counts[nbins] (host) and *n_ref receive the counts and the number of
+ * reference atoms by ADDING to what they hold, so that frames accumulate
+ * (clear them first).  g of bin b is counts[b] / (n_ref * rho_bar * 4 pi
+ * ((b+1)^3 - b^3) dr^3 / 3).  dr > 0, 1 <= nbins <= 32768.  Synchronises
+ * the context stream.  The centre of mass is summed in a fixed tree order:
+ * an atom within rounding of the r_select sphere may be classed either way. */
+int scmd_rdf(scmd_ctx *ctx, int cluster, double r_select, double dr, int nbins, uint64_t *counts,
+             int64_t *n_ref);
+
 /* Checkpoint: scmd_get_state writes a self-describing blob (positions,
  * velocities, forces, thermostat factors and settings, step counts) into buf
  * of *bytes capacity; with buf NULL it only stores the needed size in *bytes.

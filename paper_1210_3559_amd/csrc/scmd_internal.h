@@ -235,6 +235,12 @@ hipError_t launch_aos_from4(const double4 *src, double *dst, int natoms, hipStre
 // cluster: step, E_pot, E_kin, T, T_target).
 hipError_t launch_sample(const ClusterState *st, int nclusters, double *ring, int slot, int64_t step, hipStream_t s);
 
+// Pair-distance histogram of the atoms [off, off + n) (analysis.hip): refs
+// (n entries) and nref receive the reference atoms, counts (nbins) is
+// cleared and filled.
+hipError_t launch_rdf(const double4 *rp, int off, int n, double r_select, double dr, int nbins, int32_t *refs,
+                      int *nref, unsigned long long *counts, hipStream_t s);
+
 // Number of doubles per tile in tile_sums: [0] sum e_emb, [1] sum e_pair,
 // [2] sum v^2.
 constexpr int kTileSums = 4;

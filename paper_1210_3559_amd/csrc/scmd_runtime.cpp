@@ -89,6 +89,9 @@ struct scmd_ctx {
     DevBuf<ClusterDesc> d_cdesc;
     DevBuf<ClusterState> d_state;
     DevBuf<int> d_flag;
+    DevBuf<int32_t> rdf_refs;
+    DevBuf<int> rdf_nref;
+    DevBuf<unsigned long long> rdf_counts;
     int *h_flag = nullptr;  // pinned
 
     // all-pairs plan
@@ -164,6 +167,7 @@ int fail(scmd_ctx *c, int code, const std::string &msg) {
 // Batches of staged clusters (all <= kRowStageMax atoms) up to this many
 // unordered pairs per step run on the row sweeps by default.
 constexpr double kRowBatchPairs = 2.5e7;
+constexpr int kRdfMaxBins = 32768;  // LDS histogram of 128 KiB
 
 int64_t ndof_of(int64_t n) {
     if (n >= 3) return 3 * n - 6;
@@ -1444,6 +1448,36 @@ int scmd_get_density(scmd_ctx *ctx, double *out) {
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
         if (ctx->natoms > 0)
             HIP_TRY(ctx, hipMemcpy(out, ctx->rho.p, ctx->natoms * sizeof(double), hipMemcpyDeviceToHost));
+        return SCMD_OK;
+    })
+}
+
+int scmd_rdf(scmd_ctx *ctx, int cluster, double r_select, double dr, int nbins, uint64_t *counts,
+             int64_t *n_ref) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
+    if (cluster < 0 || cluster >= ctx->nclusters) return fail(ctx, SCMD_EINVAL, "cluster index out of range");
+    if (!(dr > 0.0) || !std::isfinite(dr)) return fail(ctx, SCMD_EINVAL, "need a finite dr > 0");
+    if (!std::isfinite(r_select)) return fail(ctx, SCMD_EINVAL, "r_select must be finite");
+    if (nbins < 1 || nbins > kRdfMaxBins) return fail(ctx, SCMD_EINVAL, "nbins must be in [1, 32768]");
+    if (!counts || !n_ref) return fail(ctx, SCMD_EINVAL, "counts or n_ref is NULL");
+    const int off = (int)ctx->offsets[cluster];
+    const int n = (int)(ctx->offsets[cluster + 1] - ctx->offsets[cluster]);
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        HIP_TRY(ctx, ctx->rdf_refs.ensure(std::max(n, 1)));
+        HIP_TRY(ctx, ctx->rdf_nref.ensure(1));
+        HIP_TRY(ctx, ctx->rdf_counts.ensure(nbins));
+        HIP_TRY(ctx, launch_rdf(ctx->rp.p, off, n, r_select, dr, nbins, ctx->rdf_refs.p, ctx->rdf_nref.p,
+                                ctx->rdf_counts.p, ctx->stream));
+        std::vector<unsigned long long> h(nbins);
+        int nr = 0;
+        HIP_TRY(ctx, hipMemcpyAsync(h.data(), ctx->rdf_counts.p, nbins * sizeof(unsigned long long),
+                                    hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(&nr, ctx->rdf_nref.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        for (int b = 0; b < nbins; ++b) counts[b] += h[b];
+        *n_ref += nr;
         return SCMD_OK;
     })
 }

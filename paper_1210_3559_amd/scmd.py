@@ -46,7 +46,7 @@ EXPORTS = (
     "scmd_step", "scmd_step_async", "scmd_synchronize", "scmd_get_step", "scmd_get_energy",
     "scmd_get_temperature", "scmd_get_positions", "scmd_get_velocities", "scmd_get_forces", "scmd_get_density",
     "scmd_get_forces_device", "scmd_get_state", "scmd_set_state", "scmd_set_profiling", "scmd_get_kernel_time",
-    "scmd_set_sampling", "scmd_get_samples", "scmd_last_error",
+    "scmd_set_sampling", "scmd_get_samples", "scmd_rdf", "scmd_last_error",
 )
 
 
@@ -109,6 +109,7 @@ def load(path: str = LIB_PATH):
         "scmd_get_forces": (i32, [vp, dp]),
         "scmd_get_density": (i32, [vp, dp]),
         "scmd_get_forces_device": (i32, [vp, vp]),
+        "scmd_rdf": (i32, [vp, i32, dbl, dbl, i32, vp, ctypes.POINTER(i64)]),
         "scmd_get_state": (i32, [vp, vp, ctypes.POINTER(ctypes.c_size_t)]),
         "scmd_set_state": (i32, [vp, vp, ctypes.c_size_t]),
         "scmd_set_profiling": (i32, [vp, i32]),
@@ -286,6 +287,29 @@ def scmd_get_forces_device(ctx, out_tensor) -> None:
     _check(ctx, load().scmd_get_forces_device(ctx, ctypes.c_void_p(out_tensor.data_ptr())))
 
 
+def scmd_rdf(ctx, cluster: int, dr: float, nbins: int, r_select: float = 0.0, counts=None, n_ref: int = 0):
+    """(counts uint64 (nbins,), n_ref): the pair-distance histogram of the
+    cluster's current positions, added to `counts` / `n_ref` when given (a
+    contiguous uint64 `counts` is updated in place and returned)."""
+    out = np.zeros(int(nbins), dtype=np.uint64) if counts is None else np.ascontiguousarray(counts, dtype=np.uint64)
+    if out.shape != (int(nbins),):
+        raise ValueError("counts must have nbins entries")
+    nr = ctypes.c_int64(int(n_ref))
+    _check(ctx, load().scmd_rdf(ctx, int(cluster), float(r_select), float(dr), int(nbins),
+                                out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nr)))
+    return out, int(nr.value)
+
+
+def rdf_g(counts, n_ref: int, dr: float, rho_bar: float = 4.0 / 3.52 ** 3):
+    """g(r) at the bin centres from a histogram: counts / (n_ref rho_bar
+    V_shell); rho_bar defaults to the fcc nickel number density 4/a^3."""
+    c = np.asarray(counts, dtype=np.float64)
+    b = np.arange(len(c), dtype=np.float64)
+    shell = 4.0 * np.pi / 3.0 * ((b + 1.0) ** 3 - b ** 3) * dr ** 3
+    r = (b + 0.5) * dr
+    return r, c / (max(int(n_ref), 1) * rho_bar * shell)
+
+
 def scmd_get_state(ctx) -> bytes:
     n = ctypes.c_size_t(0)
     _check(ctx, load().scmd_get_state(ctx, None, ctypes.byref(n)))
@@ -414,3 +438,6 @@ class Simulation:
 
     def samples(self, cluster: int = 0, max_samples: int = 1 << 20):
         return scmd_get_samples(self.ctx, cluster, max_samples)
+
+    def rdf(self, cluster: int, dr: float, nbins: int, r_select: float = 0.0, counts=None, n_ref: int = 0):
+        return scmd_rdf(self.ctx, cluster, dr, nbins, r_select, counts, n_ref)
