@@ -23,7 +23,7 @@ import time
 
 import numpy as np
 
-from . import inputs, scmd
+from . import diffusion, inputs, scmd
 
 K_B = 8.617333262145179e-05  # eV/K
 
@@ -96,11 +96,37 @@ def fit_rate3(T, kappa_per_ps, T0=None, p0=(1.2, 3.0e4, 1030.0)):
     return tuple(float(v) for v in p)
 
 
+def structure_series(frames, frame_ps: float, rdf_counts, rdf_nref, window_ps: float = 1000.0,
+                     stride_ps: float = 500.0, radius: float = 10.0, segments: int = 10, dr: float = 0.4):
+    """D(t) and g(r) of one trajectory as the paper computes them: at window
+    centres every stride_ps, D from the frames within +-window/2 (10
+    segments, central atoms within `radius`), g(r) of the central atoms
+    (per-frame histograms summed over the window)."""
+    fr = np.asarray(frames)
+    nwin = max(1, int(round(window_ps / frame_ps)))
+    out = []
+    centre = window_ps / 2.0
+    while (centre + window_ps / 2.0) / frame_ps <= len(fr) + 1e-9:
+        a = int(round((centre - window_ps / 2.0) / frame_ps))
+        b = min(len(fr), a + nwin)
+        d, nc = diffusion.diffusion_coefficient(fr[a:b], frame_ps, radius, segments)
+        cnt = np.sum(rdf_counts[a:b], axis=0)
+        nref = int(np.sum(rdf_nref[a:b]))
+        r, g = scmd.rdf_g(cnt, nref, dr)
+        out.append({"t_ps": centre, "D_cm2_per_s": d * diffusion.A2_PER_PS_TO_CM2_PER_S, "central_atoms": nc,
+                    "rdf_r": [float(x) for x in r], "rdf_g": [float(x) for x in g], "rdf_refs": nref})
+        centre += stride_ps
+    return out
+
+
 def run(T: float, replicas: int = 15, max_ps: float = 4000.0, T_melt: float = 1400.0, melt_ps: float = 100.0,
         gamma: float = 10.0, seed: int = 820, dt: float = 1.0, sample_ps: float = 1.0, chunk_ps: float = 100.0,
-        drop: float = 0.03, log=sys.stderr) -> dict:
+        drop: float = 0.03, track: int = 0, frame_ps: float = 10.0, rdf_select: float = 3.0, rdf_dr: float = 0.4,
+        rdf_bins: int = 40, min_ps: float = 0.0, log=sys.stderr) -> dict:
     """Melt `replicas` Mackay Ni2057 clusters at T_melt, quench them to T and
-    step until all have crystallised or max_ps has passed."""
+    step until all have crystallised or max_ps has passed.  The first
+    `track` replicas also keep a frame every frame_ps (for D(t)) and the
+    pair-distance histogram of their central atoms (for g(r))."""
     w = inputs.ni2057_cycle(replicas, seed=seed, T_low=T_melt, gamma=gamma, dt=dt)
     n = int(w.sizes()[0])
     every = max(1, int(round(sample_ps * 1000.0 / dt)))
@@ -115,9 +141,24 @@ def run(T: float, replicas: int = 15, max_ps: float = 4000.0, T_melt: float = 14
         for k in range(replicas):
             sim.set_thermostat(k, dict(w.thermostat[k], T_start=T, T_end=T, ramp_steps=0))
         done, found = 0, [None] * replicas
+        fstep = max(every, int(round(frame_ps * 1000.0 / dt)) // every * every) if track > 0 else chunk
+        frames = [[] for _ in range(track)]
+        hists = [[] for _ in range(track)]
+        nrefs = [[] for _ in range(track)]
         while done < max_steps:
             c = min(chunk, max_steps - done)
-            sim.step(c)
+            left = c
+            while left > 0:
+                f = min(fstep, left)
+                sim.step(f)
+                left -= f
+                if track > 0 and f == fstep:
+                    pos = sim.positions()
+                    for k in range(track):
+                        frames[k].append(pos[w.offsets[k]:w.offsets[k + 1]].copy())
+                        h, nr = sim.rdf(k, rdf_dr, rdf_bins, rdf_select)
+                        hists[k].append(h)
+                        nrefs[k].append(nr)
             done += c
             for k in range(replicas):
                 if found[k] is None:
@@ -128,7 +169,7 @@ def run(T: float, replicas: int = 15, max_ps: float = 4000.0, T_melt: float = 14
             nf = sum(x is not None for x in found)
             print(f"[kinetics] T={T:.0f} K: {done * dt * 1e-3:.0f} ps, {nf}/{replicas} crystallised, "
                   f"{time.perf_counter() - t0:.1f} s", file=log, flush=True)
-            if nf == replicas:
+            if nf == replicas and done * dt * 1e-3 >= min_ps:
                 break
         traces = []
         for k in range(replicas):
@@ -147,8 +188,11 @@ def run(T: float, replicas: int = 15, max_ps: float = 4000.0, T_melt: float = 14
             liq = np.median(ek[(tk >= 10.0) & (tk <= max(20.0, x - 5.0))])
             sol = np.median(ek[tk >= tk[-1] - 30.0])
             lat.append(float(liq - sol) * n)
+    series = [structure_series(frames[k], frame_ps, hists[k], nrefs[k], dr=rdf_dr) for k in range(track)
+              if len(frames[k]) * frame_ps >= 1000.0]
     return {
         "T_K": T, "replicas": replicas, "atoms_per_cluster": n, "gamma_per_ps": gamma, "dt_fs": dt,
+        "tracked": series,
         "melt": {"T_K": T_melt, "ps": melt_steps * dt * 1e-3}, "max_ps": max_ps, "run_ps": run_ps,
         "lifetimes_ps": [x for x in found], "n_crystallised": len(life), "mean_lifetime_ps": (
             float(np.mean(life)) if life else None),
@@ -165,13 +209,17 @@ def main(argv=None) -> int:
     ap.add_argument("--replicas", type=int, default=15)
     ap.add_argument("--max-ps", type=float, default=4000.0)
     ap.add_argument("--seed", type=int, default=820)
+    ap.add_argument("--track", type=int, default=0, help="replicas whose D(t) and g(r) are recorded")
+    ap.add_argument("--min-ps", type=float, default=0.0, help="run at least this long")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
-    res = run(args.T, args.replicas, args.max_ps, seed=args.seed)
+    res = run(args.T, args.replicas, args.max_ps, seed=args.seed, track=args.track, min_ps=args.min_ps)
     if args.out:
         with open(args.out, "w") as f:
             json.dump(res, f)
-    print(json.dumps({k: v for k, v in res.items() if k != "traces"}))
+    brief = {k: v for k, v in res.items() if k not in ("traces", "tracked")}
+    brief["D_cm2_per_s"] = [[(round(x["t_ps"]), x["D_cm2_per_s"]) for x in s] for s in res["tracked"]]
+    print(json.dumps(brief))
     return 0
 
 

@@ -75,3 +75,15 @@ def test_no_transition_is_censored():
     t = np.arange(0.0, 1000.0, 1.0)
     e = -3.95 + rng.normal(0, 0.003, t.size) + 1e-6 * t
     assert kinetics.transition_time(t, e, drop=0.03) is None
+
+
+def test_structure_series_windows():
+    rng = np.random.default_rng(0)
+    frames = np.cumsum(rng.normal(0, 0.2, (300, 400, 3)), axis=0) + rng.uniform(-8, 8, (400, 3))
+    hist = [np.arange(40, dtype=np.uint64)] * 300
+    out = kinetics.structure_series(frames, 10.0, hist, [3] * 300, radius=1e9)
+    # 3 ns of frames: 1 ns windows centred every 0.5 ns
+    assert [o["t_ps"] for o in out] == [500.0, 1000.0, 1500.0, 2000.0, 2500.0]
+    for o in out:
+        assert o["rdf_refs"] == 300  # 100 frames x 3 reference atoms
+        assert o["D_cm2_per_s"] == pytest.approx(0.2 ** 2 / 20.0 * 1e-4, rel=0.1)
