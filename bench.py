@@ -259,6 +259,8 @@ def main(argv=None):
                    "pairs_per_step": main_res.get("pairs_per_step"), "parallelism": "single_gpu"},
         "pair_interactions_per_s": main_res.get("pair_interactions_per_s"),
         "roofline": main_res.get("roofline"),
+        "kernel_timing": {k: main_res.get(k) for k in ("force_ms_per_launch", "force_launches_timed",
+                                                       "density_ms_per_launch")},
         "cpu_baseline": cpu,
         "forms": forms,
     }
