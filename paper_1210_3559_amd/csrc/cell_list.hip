@@ -18,10 +18,10 @@
 //   order   per cell: every atom's slot becomes its rank by atom index, so
 //           the cell-sorted order is deterministic; positions are gathered.
 // Sweeps: one workgroup per cell; its atoms are the lanes (64 at a time),
-// three wavefronts split the 27 neighbouring cells, read as 9 contiguous
-// x-rows of the sorted arrays with wave-uniform scalar loads.  Every atom's sum is complete after one sweep, so the tiles
-// of the all-pairs plan are finished by the same reduce kernels with one
-// slot per tile.
+// eight wavefronts split the candidates of the 27 neighbouring cells (9
+// contiguous x-rows of the sorted arrays, staged in LDS).  Every atom's sum is
+// complete after one sweep, so the tiles of the all-pairs plan are finished
+// by the same reduce kernels with one slot per tile.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -274,11 +274,16 @@ __global__ __launch_bounds__(256) void k_cell_gather_p(const int *__restrict__ s
 // ---------------------------------------------------------------------------
 // Sweeps
 // ---------------------------------------------------------------------------
-// One workgroup of kCellWaves wavefronts per cell.  All wavefronts hold the
-// same 64 atoms of the cell (more in chunks of 64) and split the 9 neighbour
-// rows between them (wavefront w takes rows w, w + W, ...); their sums are
-// combined in LDS in wavefront order.
-constexpr int kCellWaves = 3;
+// One workgroup of kCellWaves wavefronts per cell.  The cell's 27-cell
+// neighbourhood is 9 x-rows, each contiguous in the sorted arrays; their
+// atoms (the candidates, concatenated row after row) are staged in LDS when
+// they fit.  The cell's atoms are the lanes (64 at a time); wavefront w takes
+// the w-th of kCellWaves equal contiguous shares of the candidates, and the
+// shares are added in wavefront order (deterministic).  Neighbourhoods larger
+// than the LDS buffer (only when cells coarsened after an atom escaped) read
+// the same candidates from global memory.
+constexpr int kCellWaves = 8;
+constexpr int kCellStage = 2000;  // staged candidates (62.5 KiB: two workgroups per CU)
 
 template <int PREC, bool GEN, bool FORCE>
 __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *__restrict__ grid,
@@ -290,15 +295,46 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
                                                                 double *__restrict__ part, int tile_shift,
                                                                 PotConst pc) {
     constexpr int Q = FORCE ? 4 : 1;
+    extern __shared__ double4 lj[];
     __shared__ double sh[kCellWaves * Q * 64];
+    __shared__ int seg_lo[9], seg_len[9], seg_off[10];
     const int cell = blockIdx.x;
     const CellGrid g = grid[cell_cluster[cell]];
     const int local = cell - g.base;
-    if (local >= g.nx * g.ny * g.nz) return;
+    if (local >= g.nx * g.ny * g.nz) return;  // uniform per workgroup
     const int s0 = start[cell], cnt = start[cell + 1] - s0;
     if (cnt == 0) return;
     const int ix = local % g.nx, iy = (local / g.nx) % g.ny, iz = local / (g.nx * g.ny);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < 9) {
+        const int jz = iz + tid / 3 - 1, jy = iy + tid % 3 - 1;
+        int ja = 0, jb = 0;
+        if (jz >= 0 && jz < g.nz && jy >= 0 && jy < g.ny) {
+            const int row = g.base + (jz * g.ny + jy) * g.nx;
+            ja = start[row + max(ix - 1, 0)];
+            jb = start[row + min(ix + 1, g.nx - 1) + 1];
+        }
+        seg_lo[tid] = ja;
+        seg_len[tid] = jb - ja;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        seg_off[0] = 0;
+        for (int r = 0; r < 9; ++r) seg_off[r + 1] = seg_off[r] + seg_len[r];
+    }
+    __syncthreads();
+    const int M = seg_off[9];
+    const bool staged = M <= kCellStage;
+    if (staged) {
+        for (int p = tid; p < M; p += 64 * kCellWaves) {
+            int r = 0;
+            while (p >= seg_off[r + 1]) ++r;
+            lj[p] = rs[seg_lo[r] + (p - seg_off[r])];
+        }
+    }
+    __syncthreads();
+    // this wavefront's share of the candidates
+    const int pa = (int)(((long long)M * wave) / kCellWaves), pb = (int)(((long long)M * (wave + 1)) / kCellWaves);
     const int tile = 1 << tile_shift;
     const float Af = (float)pc.A;
     for (int ci = 0; ci < cnt; ci += 64) {
@@ -316,30 +352,17 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
         double acc[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) acc[q] = 0.0;
-        for (int r = wave; r < 9; r += kCellWaves) {
-            const int jz = iz + r / 3 - 1, jy = iy + r % 3 - 1;
-            if (jz < 0 || jz >= g.nz || jy < 0 || jy >= g.ny) continue;
-            const int row = g.base + (jz * g.ny + jy) * g.nx;
-            const int ja = start[row + max(ix - 1, 0)];
-            const int jb = start[row + min(ix + 1, g.nx - 1) + 1];
-            if (r == 4) {  // own row: contains the self pairs
-                for (int j = ja; j < jb; ++j) {
-                    const double4 q = rs[j];
-                    if constexpr (FORCE)
-                        force_pair<PREC, GEN, true, true>(xi - q.x, yi - q.y, zi - q.z, j == k, c_i, q.w, cif,
-                                                          (float)q.w, acc[0], acc[1], acc[2], acc[3], pc, Af);
-                    else
-                        density_pair<PREC, GEN, true, true>(xi - q.x, yi - q.y, zi - q.z, j == k, acc[0], pc);
-                }
-            } else {
-                for (int j = ja; j < jb; ++j) {
-                    const double4 q = rs[j];
-                    if constexpr (FORCE)
-                        force_pair<PREC, GEN, false, true>(xi - q.x, yi - q.y, zi - q.z, false, c_i, q.w, cif,
-                                                           (float)q.w, acc[0], acc[1], acc[2], acc[3], pc, Af);
-                    else
-                        density_pair<PREC, GEN, false, true>(xi - q.x, yi - q.y, zi - q.z, false, acc[0], pc);
-                }
+        for (int r = 0; r < 9; ++r) {
+            const int lo = max(pa, seg_off[r]), hi = min(pb, seg_off[r + 1]);
+            const int jbase = seg_lo[r] - seg_off[r];  // candidate p is sorted atom jbase + p
+            for (int p = lo; p < hi; ++p) {
+                const double4 q = staged ? lj[p] : rs[jbase + p];
+                const bool self = jbase + p == k;
+                if constexpr (FORCE)
+                    force_pair<PREC, GEN, true, true>(xi - q.x, yi - q.y, zi - q.z, self, c_i, q.w, cif,
+                                                      (float)q.w, acc[0], acc[1], acc[2], acc[3], pc, Af);
+                else
+                    density_pair<PREC, GEN, true, true>(xi - q.x, yi - q.y, zi - q.z, self, acc[0], pc);
             }
         }
         if constexpr (FORCE) unscale_force<PREC, GEN>(acc[0], acc[1], acc[2], acc[3]);
@@ -373,17 +396,18 @@ template <bool FORCE>
 hipError_t launch_cell_sweep(CellList *cl, double *part, const PotConst &pc, int precision, hipStream_t s) {
     (void)hipGetLastError();
     const dim3 grid(cl->total_cap), block(64 * kCellWaves);
+    const size_t lds = kCellStage * sizeof(double4);
 #define SCMD_CELL_ARGS cl->grid, cl->cell_cluster, cl->start, cl->rs, cl->sperm, cl->pslot, part, cl->tile_shift, pc
     if (precision == SCMD_FP64) {
         if (pc.generic)
-            hipLaunchKernelGGL((k_cell_sweep<SCMD_FP64, true, FORCE>), grid, block, 0, s, SCMD_CELL_ARGS);
+            hipLaunchKernelGGL((k_cell_sweep<SCMD_FP64, true, FORCE>), grid, block, lds, s, SCMD_CELL_ARGS);
         else
-            hipLaunchKernelGGL((k_cell_sweep<SCMD_FP64, false, FORCE>), grid, block, 0, s, SCMD_CELL_ARGS);
+            hipLaunchKernelGGL((k_cell_sweep<SCMD_FP64, false, FORCE>), grid, block, lds, s, SCMD_CELL_ARGS);
     } else {
         if (pc.generic)
-            hipLaunchKernelGGL((k_cell_sweep<SCMD_MIXED, true, FORCE>), grid, block, 0, s, SCMD_CELL_ARGS);
+            hipLaunchKernelGGL((k_cell_sweep<SCMD_MIXED, true, FORCE>), grid, block, lds, s, SCMD_CELL_ARGS);
         else
-            hipLaunchKernelGGL((k_cell_sweep<SCMD_MIXED, false, FORCE>), grid, block, 0, s, SCMD_CELL_ARGS);
+            hipLaunchKernelGGL((k_cell_sweep<SCMD_MIXED, false, FORCE>), grid, block, lds, s, SCMD_CELL_ARGS);
     }
 #undef SCMD_CELL_ARGS
     return hipGetLastError();
