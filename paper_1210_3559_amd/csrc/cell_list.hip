@@ -355,6 +355,8 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
         for (int r = 0; r < 9; ++r) {
             const int lo = max(pa, seg_off[r]), hi = min(pb, seg_off[r + 1]);
             const int jbase = seg_lo[r] - seg_off[r];  // candidate p is sorted atom jbase + p
+            // unrolled: independent pair chains interleave with the LDS reads
+#pragma unroll 4
             for (int p = lo; p < hi; ++p) {
                 const double4 q = staged ? lj[p] : rs[jbase + p];
                 const bool self = jbase + p == k;
