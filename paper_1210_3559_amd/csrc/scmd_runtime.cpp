@@ -645,7 +645,7 @@ SweepBuffers buffers(scmd_ctx *c) {
 
 // One pair sweep (with its profiling events).  energy = 0 lets the force
 // sweep skip the pair energy (steps whose energies nobody reads).  Row
-// sweeps of one staged cluster take the drift (drift_mode, local: RowDrift)
+// sweeps of staged clusters take the drift (drift_mode, local: RowDrift)
 // and the fused force epilogue.
 hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int advance, int energy = 1,
                  int drift_mode = 0, int local = 0, int fused = 0) {

@@ -283,7 +283,7 @@ struct ForceOut {
     double4 *rp;
     double2 *dpv;  // drift inputs of the next step (p, v); Langevin: the drifted (r, v)
     double dth;    // dt h
-    // Langevin epilogue (fused = 2): cluster 0's bath, the run's step index
+    // bath epilogue of clusters in a Langevin bath: their baths, the run's step index
     const ClusterDesc *cd;
     int local;
     double dt, mass_u;
