@@ -17,11 +17,12 @@
 //   scatter per atom: a slot in its cell (atomic cursor);
 //   order   per cell: every atom's slot becomes its rank by atom index, so
 //           the cell-sorted order is deterministic; positions are gathered.
-// Sweeps: one workgroup per cell; its atoms are the lanes (64 at a time),
-// eight wavefronts split the candidates of the 27 neighbouring cells (9
-// contiguous x-rows of the sorted arrays, staged in LDS).  Every atom's sum is
-// complete after one sweep, so the tiles of the all-pairs plan are finished
-// by the same reduce kernels with one slot per tile.
+// Sweeps: one workgroup per cell; the candidates of the 27 neighbouring cells
+// (9 contiguous x-rows of the sorted arrays) are staged in LDS, and each
+// wavefront takes the cell's atoms one at a time with its lanes across the
+// candidates.  Every atom's sum is complete after one sweep, so the tiles of
+// the all-pairs plan are finished by the same reduce kernels with one slot
+// per tile.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -277,13 +278,21 @@ __global__ __launch_bounds__(256) void k_cell_gather_p(const int *__restrict__ s
 // One workgroup of kCellWaves wavefronts per cell.  The cell's 27-cell
 // neighbourhood is 9 x-rows, each contiguous in the sorted arrays; their
 // atoms (the candidates, concatenated row after row) are staged in LDS when
-// they fit.  The cell's atoms are the lanes (64 at a time); wavefront w takes
-// the w-th of kCellWaves equal contiguous shares of the candidates, and the
-// shares are added in wavefront order (deterministic).  Neighbourhoods larger
-// than the LDS buffer (only when cells coarsened after an atom escaped) read
-// the same candidates from global memory.
+// they fit.  Wavefront w takes the cell's atoms w, w + kCellWaves, ... one at
+// a time; for each, its lanes sweep the candidates (lane l takes l, l + 64,
+// ...) and a fixed-order butterfly adds the 64 lane sums, so every atom's sum
+// has one order whatever the launch (deterministic).  The atom itself sits
+// in the own row at one known candidate index (the self pair).
+// Neighbourhoods larger than the LDS buffer (only when cells coarsened after
+// an atom escaped) read the same candidates from global memory.
 constexpr int kCellWaves = 8;
 constexpr int kCellStage = 2000;  // staged candidates (62.5 KiB: two workgroups per CU)
+
+__device__ __forceinline__ double lane_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
 
 template <int PREC, bool GEN, bool FORCE>
 __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *__restrict__ grid,
@@ -296,7 +305,6 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
                                                                 PotConst pc) {
     constexpr int Q = FORCE ? 4 : 1;
     extern __shared__ double4 lj[];
-    __shared__ double sh[kCellWaves * Q * 64];
     __shared__ int seg_lo[9], seg_len[9], seg_off[10];
     const int cell = blockIdx.x;
     const CellGrid g = grid[cell_cluster[cell]];
@@ -325,72 +333,55 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
     __syncthreads();
     const int M = seg_off[9];
     const bool staged = M <= kCellStage;
+    // sorted atom of candidate p (p < M)
+    auto cand = [&](int p) {
+        int r = 0;
+        while (p >= seg_off[r + 1]) ++r;
+        return seg_lo[r] + (p - seg_off[r]);
+    };
     if (staged) {
-        for (int p = tid; p < M; p += 64 * kCellWaves) {
-            int r = 0;
-            while (p >= seg_off[r + 1]) ++r;
-            lj[p] = rs[seg_lo[r] + (p - seg_off[r])];
-        }
+        for (int p = tid; p < M; p += 64 * kCellWaves) lj[p] = rs[cand(p)];
     }
     __syncthreads();
-    // this wavefront's share of the candidates
-    const int pa = (int)(((long long)M * wave) / kCellWaves), pb = (int)(((long long)M * (wave + 1)) / kCellWaves);
     const int tile = 1 << tile_shift;
     const float Af = (float)pc.A;
-    for (int ci = 0; ci < cnt; ci += 64) {
-        const bool valid = ci + lane < cnt;
-        const int k = s0 + ci + lane;
-        double xi = -kFar, yi = -kFar, zi = -kFar, c_i = 0.0;
-        if (valid) {
-            const double4 q = rs[k];
-            xi = q.x;
-            yi = q.y;
-            zi = q.z;
-            c_i = -q.w;
-        }
+    // the own cell lies in the own row (segment 4): atom k is candidate
+    // seg_off[4] + (k - seg_lo[4])
+    const int self0 = seg_off[4] - seg_lo[4];
+    for (int a = wave; a < cnt; a += kCellWaves) {
+        const int k = s0 + a;
+        const double4 qi = rs[k];
+        const double c_i = -qi.w;
         const float cif = (float)c_i;
+        const int self_p = self0 + k;
         double acc[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) acc[q] = 0.0;
-        for (int r = 0; r < 9; ++r) {
-            const int lo = max(pa, seg_off[r]), hi = min(pb, seg_off[r + 1]);
-            const int jbase = seg_lo[r] - seg_off[r];  // candidate p is sorted atom jbase + p
-            // unrolled: independent pair chains interleave with the LDS reads
-#pragma unroll 4
-            for (int p = lo; p < hi; ++p) {
-                const double4 q = staged ? lj[p] : rs[jbase + p];
-                const bool self = jbase + p == k;
-                if constexpr (FORCE)
-                    force_pair<PREC, GEN, true, true>(xi - q.x, yi - q.y, zi - q.z, self, c_i, q.w, cif,
-                                                      (float)q.w, acc[0], acc[1], acc[2], acc[3], pc, Af);
-                else
-                    density_pair<PREC, GEN, true, true>(xi - q.x, yi - q.y, zi - q.z, self, acc[0], pc);
-            }
+#pragma unroll 2
+        for (int p = lane; p < M; p += 64) {
+            const double4 q = staged ? lj[p] : rs[cand(p)];
+            if constexpr (FORCE)
+                force_pair<PREC, GEN, true, true>(qi.x - q.x, qi.y - q.y, qi.z - q.z, p == self_p, c_i, q.w, cif,
+                                                  (float)q.w, acc[0], acc[1], acc[2], acc[3], pc, Af);
+            else
+                density_pair<PREC, GEN, true, true>(qi.x - q.x, qi.y - q.y, qi.z - q.z, p == self_p, acc[0], pc);
         }
         if constexpr (FORCE) unscale_force<PREC, GEN>(acc[0], acc[1], acc[2], acc[3]);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) sh[(wave * Q + q) * 64 + lane] = acc[q];
-        __syncthreads();
-        if (wave == 0 && valid) {
-            double tot[Q];
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                tot[q] = sh[q * 64 + lane];
-                for (int w = 1; w < kCellWaves; ++w) tot[q] += sh[(w * Q + q) * 64 + lane];
-            }
+        for (int q = 0; q < Q; ++q) acc[q] = lane_sum(acc[q]);
+        if (lane == 0) {
             const int ps = pslot[sperm[k]];
             if constexpr (FORCE) {
                 const int t = ps >> tile_shift, li = ps & (tile - 1);
                 double *out = part + (size_t)t * 4 * tile + li;
-                out[0] = tot[0];
-                out[tile] = tot[1];
-                out[2 * tile] = tot[2];
-                out[3 * tile] = tot[3];
+                out[0] = acc[0];
+                out[tile] = acc[1];
+                out[2 * tile] = acc[2];
+                out[3 * tile] = acc[3];
             } else {
-                part[ps] = tot[0];
+                part[ps] = acc[0];
             }
         }
-        __syncthreads();
     }
 }
 
