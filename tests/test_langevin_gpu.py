@@ -43,6 +43,7 @@ def _run(w_off, pos, vel, dt, baths, chunks, precision="fp64", tuning=None, rc=0
 
 PATHS = {
     "row_fused": (None, "fp64", 0.0),
+    "mixed_symmetric": (dict(pairs=2, ipt=4), "mixed", 0.0),
     "symmetric": (dict(pairs=2, ipt=4), "fp64", 0.0),
     "one_sided": (dict(pairs=1, ipt=1, waves_i=1, waves_j=4), "fp64", 0.0),
     "row_waves4": (dict(pairs=3, waves_j=4), "fp64", 0.0),
@@ -238,3 +239,21 @@ def test_two_leg_temperature_programme(kind):
     np.testing.assert_array_equal(smp[:, 4], np.concatenate([l1[:, 3], l2[:, 3]]))
     assert np.abs(r - r2).max() < 1e-9
     assert np.abs(v - v2).max() < 1e-10
+
+
+@pytest.mark.parametrize("tuning", [None, dict(pairs=1, ipt=1, waves_i=1, waves_j=4)])
+def test_langevin_with_generic_exponents(tuning):
+    # (n, m) = (12, 6): the generic-exponent kernels carry the same bath code
+    params = dict(n=12, m=6)
+    w = inputs.c1_icosahedron()
+    th = _bath(700.0, seed=12, T_start=1000.0, ramp=30)
+    print(f"[langevin] generic exponents tuning={tuning}", flush=True)
+    r_ref, v_ref, _, log = oracle.vv_run(w.pos, w.vel, 45, dt=1.0, thermostat=th, params=params, nthreads=NT)
+    with scmd.Simulation(w.offsets, w.pos, w.vel, dt=1.0, thermostats=[th], tuning=tuning, params=params) as sim:
+        sim.step(13)
+        sim.step(32)
+        r, v = sim.positions(), sim.velocities()
+        ep = sim.energy(0)[0]
+    assert np.abs(r - r_ref).max() < 1e-9
+    assert np.abs(v - v_ref).max() < 1e-10
+    assert ep == pytest.approx(log[-1, 0], rel=1e-10)
