@@ -11,13 +11,17 @@
 // each j tile is loaded one atom per lane and then rotated through the
 // wavefront with DPP wave_ror:1 64 times, so that every lane meets every j
 // atom; the j tile carries its own force (or density) accumulators along.
-// Pairs inside a group are done one-sidedly by a separate diagonal item.
+// Pairs inside a group are done by a separate diagonal item, in which the
+// group's own tiles rotate past it the same way: a pair of different tiles
+// is evaluated once (its j sums return to their home lanes after the 64
+// rotations and join the i sums of their tile), a pair inside one tile
+// one-sidedly from both ends.
 //
 // Outputs are partial sums: the i side per item, the j side per (group,
 // tile).  The reduce kernels add, for every atom, its group's i-side items in
 // item order and then the j-side partials of every earlier group in group
 // order: the result is deterministic.  Pair energy: each unordered pair adds
-// 2 u^n to the i side (diagonal items add u^n per ordered pair), so
+// 2 u^n to the i side (pairs inside a tile add u^n per ordered pair), so
 // E_pair = (eps/2) a^n sum over all atoms, as in the one-sided sweeps.
 #include "sweep_common.h"
 
@@ -123,19 +127,51 @@ __global__ __launch_bounds__(64) void k_sym_force(const SymItem *__restrict__ it
         cif[p] = (float)G.c[p];
     }
     if (it.b0 == it.b1) {
-        // diagonal item: every ordered pair inside the group, one-sided
-        const SymTile first = tiles[it.t0];
-        const SymTile last = tiles[it.t0 + it.ng - 1];
-        const int ja = first.i0, jb = last.i0 + last.ni;
-        for (int j = ja; j < jb; ++j) {
-            const double4 q = xp[j];
-            const float pjf = (float)q.w;
+        // diagonal item: the group's own tile b rotates past tiles p <= b
+        double eus[IPT];  // energy of the pairs of different tiles (counted twice below)
 #pragma unroll
-            for (int p = 0; p < IPT; ++p) {
-                force_pair<PREC, false, true, false>(G.x[p] - q.x, G.y[p] - q.y, G.z[p] - q.z, G.gi[p] == j, G.c[p],
-                                                     q.w, cif[p], pjf, fx[p], fy[p], fz[p], eu[p], pc, Af);
+        for (int p = 0; p < IPT; ++p) eus[p] = 0.0;
+#pragma unroll
+        for (int b = 0; b < IPT; ++b) {
+            if (b < it.ng) {
+                const bool own = G.gi[b] >= 0;  // past the tile's atoms: the j sentinel
+                double xj = own ? G.x[b] : kFar, yj = own ? G.y[b] : kFar, zj = own ? G.z[b] : kFar;
+                double pj = own ? -G.c[b] : 0.0;
+                double gx = 0.0, gy = 0.0, gz = 0.0;
+                // rotation k: lane l meets atom l - k of tile b; k = 0 is the
+                // self pair inside tile b
+                auto step = [&](bool with_own_tile) {
+                    const float pjf = (float)pj;
+#pragma unroll
+                    for (int p = 0; p < IPT; ++p) {
+                        if (p < b) {
+                            sym_force_pair<PREC, EN>(G.x[p] - xj, G.y[p] - yj, G.z[p] - zj, G.c[p], pj, cif[p], pjf,
+                                                     fx[p], fy[p], fz[p], eus[p], gx, gy, gz, pc, Af);
+                        } else if (p == b && with_own_tile) {
+                            double hx = 0.0, hy = 0.0, hz = 0.0;  // one-sided: no j sums
+                            sym_force_pair<PREC, EN>(G.x[p] - xj, G.y[p] - yj, G.z[p] - zj, G.c[p], pj, cif[p], pjf,
+                                                     fx[p], fy[p], fz[p], eu[p], hx, hy, hz, pc, Af);
+                        }
+                    }
+                    xj = ror1(xj);
+                    yj = ror1(yj);
+                    zj = ror1(zj);
+                    pj = ror1(pj);
+                    gx = ror1(gx);
+                    gy = ror1(gy);
+                    gz = ror1(gz);
+                };
+                step(false);
+#pragma unroll 2
+                for (int k = 1; k < 64; ++k) step(true);
+                // after 64 rotations the j sums are back in their home lanes
+                fx[b] += gx;
+                fy[b] += gy;
+                fz[b] += gz;
             }
         }
+#pragma unroll
+        for (int p = 0; p < IPT; ++p) eu[p] += 2.0 * eus[p];
     } else {
         for (int b = it.b0; b < it.b1; ++b) {
             const SymTile t = tiles[b];
@@ -192,6 +228,18 @@ __global__ __launch_bounds__(64) void k_sym_force(const SymItem *__restrict__ it
 // ---------------------------------------------------------------------------
 // Density sweep
 // ---------------------------------------------------------------------------
+// (a/r)^m / a^m = u^6 of one pair ((n, m) = (9, 6)).
+template <int PREC>
+__device__ __forceinline__ double sym_density_term(double dx, double dy, double dz) {
+    if constexpr (PREC == SCMD_FP64) {
+        const double w = rcp_nr(__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)));
+        return w * w * w;
+    } else {
+        const float w = __builtin_amdgcn_rcpf((float)__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)));
+        return (double)(w * w * w);
+    }
+}
+
 template <int IPT, int PREC>
 __global__ __launch_bounds__(64) void k_sym_density(const SymItem *__restrict__ items,
                                                     const int32_t *__restrict__ order,
@@ -206,15 +254,34 @@ __global__ __launch_bounds__(64) void k_sym_density(const SymItem *__restrict__ 
 #pragma unroll
     for (int p = 0; p < IPT; ++p) acc[p] = 0.0;
     if (it.b0 == it.b1) {
-        const SymTile first = tiles[it.t0];
-        const SymTile last = tiles[it.t0 + it.ng - 1];
-        const int ja = first.i0, jb = last.i0 + last.ni;
-        for (int j = ja; j < jb; ++j) {
-            const double4 q = rp[j];
+        // diagonal item (as in the force sweep): tile b rotates past tiles p <= b
 #pragma unroll
-            for (int p = 0; p < IPT; ++p)
-                density_pair<PREC, false, true, false>(G.x[p] - q.x, G.y[p] - q.y, G.z[p] - q.z, G.gi[p] == j, acc[p],
-                                                       pc);
+        for (int b = 0; b < IPT; ++b) {
+            if (b < it.ng) {
+                const bool own = G.gi[b] >= 0;
+                double xj = own ? G.x[b] : kFar, yj = own ? G.y[b] : kFar, zj = own ? G.z[b] : kFar;
+                double rj = 0.0;
+                auto step = [&](bool with_own_tile) {
+#pragma unroll
+                    for (int p = 0; p < IPT; ++p) {
+                        if (p < b) {
+                            const double t6 = sym_density_term<PREC>(G.x[p] - xj, G.y[p] - yj, G.z[p] - zj);
+                            acc[p] += t6;
+                            rj += t6;
+                        } else if (p == b && with_own_tile) {
+                            acc[p] += sym_density_term<PREC>(G.x[p] - xj, G.y[p] - yj, G.z[p] - zj);
+                        }
+                    }
+                    xj = ror1(xj);
+                    yj = ror1(yj);
+                    zj = ror1(zj);
+                    rj = ror1(rj);
+                };
+                step(false);
+#pragma unroll 2
+                for (int k = 1; k < 64; ++k) step(true);
+                acc[b] += rj;
+            }
         }
     } else {
         for (int b = it.b0; b < it.b1; ++b) {
@@ -231,15 +298,7 @@ __global__ __launch_bounds__(64) void k_sym_density(const SymItem *__restrict__ 
             for (int k = 0; k < 64; ++k) {
 #pragma unroll
                 for (int p = 0; p < IPT; ++p) {
-                    const double dx = G.x[p] - xj, dy = G.y[p] - yj, dz = G.z[p] - zj;
-                    double t6;
-                    if constexpr (PREC == SCMD_FP64) {
-                        const double w = rcp_nr(__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)));
-                        t6 = w * w * w;
-                    } else {
-                        const float w = __builtin_amdgcn_rcpf((float)__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)));
-                        t6 = (double)(w * w * w);
-                    }
+                    const double t6 = sym_density_term<PREC>(G.x[p] - xj, G.y[p] - yj, G.z[p] - zj);
                     acc[p] += t6;
                     rj += t6;
                 }
