@@ -356,11 +356,34 @@ __device__ __forceinline__ double thermostat_lambda(const ClusterDesc &d, double
 }
 
 // Fixed-order totals of a cluster's tile sums: threads 0..255 add every
-// 256th tile, each of the four wavefronts folds its lanes with an xor
-// butterfly (the value of lane 0 is used), and the four wavefront sums are
-// added as (w0 + w1) + (w2 + w3).  Any workgroup of >= 256 threads gets the
-// same bits; every thread must call it.  sh needs 12 doubles.  With V2_ONLY
-// only the v^2 column is read (the others come back as 0).
+// 256th tile, each of the four wavefronts folds its lanes with wave_total,
+// and the four wavefront sums are added as (w0 + w1) + (w2 + w3).  Any
+// workgroup of >= 256 threads gets the same bits; every thread must call it.
+// sh needs 12 doubles.  With V2_ONLY only the v^2 column is read (the others
+// come back as 0).
+// Sum of a double over the 64 lanes of a fully active wavefront with DPP
+// moves, in one fixed order: pairs and quads (quad_perm), 8 and 16 lanes
+// (row_half_mirror, row_mirror), then the four rows of 16 (row_bcast15 into
+// rows 1 and 3, row_bcast31 into rows 2 and 3); lane 63 ends with
+// (r0 + r1) + (r2 + r3) and its value is returned to every lane.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_add_src(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_total(double x) {
+    x += dpp_add_src<0xB1, 0xF>(x);
+    x += dpp_add_src<0x4E, 0xF>(x);
+    x += dpp_add_src<0x141, 0xF>(x);
+    x += dpp_add_src<0x140, 0xF>(x);
+    x += dpp_add_src<0x142, 0xA>(x);
+    x += dpp_add_src<0x143, 0xC>(x);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), 63);
+    return __hiloint2double(hi, lo);
+}
+
 constexpr int kTotBlock = 256;
 template <bool V2_ONLY>
 __device__ __forceinline__ void cluster_totals(const ClusterDesc &d, const double *tile_sums, double *sh,
@@ -377,14 +400,11 @@ __device__ __forceinline__ void cluster_totals(const ClusterDesc &d, const doubl
             v2 += ts[2];
         }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        if constexpr (!V2_ONLY) {
-            emb += __shfl_xor(emb, o, 64);
-            epair += __shfl_xor(epair, o, 64);
-        }
-        v2 += __shfl_xor(v2, o, 64);
+    if constexpr (!V2_ONLY) {
+        emb = wave_total(emb);
+        epair = wave_total(epair);
     }
+    v2 = wave_total(v2);
     if (t < kTotBlock && (t & 63) == 0) {
         const int w = t >> 6;
         sh[w] = emb;

@@ -128,12 +128,9 @@ __device__ __forceinline__ void row_reduce(const RowLayout &L, double (&v)[Q], d
     }
 }
 
-// Wavefront sum (fixed butterfly, deterministic) of lanes 0..63.
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
+// Wavefront sum (fixed DPP order, deterministic) of lanes 0..63; the whole
+// wavefront must be active.
+__device__ __forceinline__ double wave_sum(double x) { return wave_total(x); }
 
 // The workgroup's tile: from the arguments for a single cluster with equal
 // runs (no table loads), else from the tables in launch order.
