@@ -280,19 +280,13 @@ __global__ __launch_bounds__(256) void k_cell_gather_p(const int *__restrict__ s
 // atoms (the candidates, concatenated row after row) are staged in LDS when
 // they fit.  Wavefront w takes the cell's atoms w, w + kCellWaves, ... one at
 // a time; for each, its lanes sweep the candidates (lane l takes l, l + 64,
-// ...) and a fixed-order butterfly adds the 64 lane sums, so every atom's sum
+// ...) and a fixed-order DPP reduction adds the 64 lane sums, so every atom's sum
 // has one order whatever the launch (deterministic).  The atom itself sits
 // in the own row at one known candidate index (the self pair).
 // Neighbourhoods larger than the LDS buffer (only when cells coarsened after
 // an atom escaped) read the same candidates from global memory.
 constexpr int kCellWaves = 8;
 constexpr int kCellStage = 2000;  // staged candidates (62.5 KiB: two workgroups per CU)
-
-__device__ __forceinline__ double lane_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 template <int PREC, bool GEN, bool FORCE>
 __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *__restrict__ grid,
@@ -368,7 +362,7 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
         }
         if constexpr (FORCE) unscale_force<PREC, GEN>(acc[0], acc[1], acc[2], acc[3]);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) acc[q] = lane_sum(acc[q]);
+        for (int q = 0; q < Q; ++q) acc[q] = wave_total(acc[q]);
         if (lane == 0) {
             const int ps = pslot[sperm[k]];
             if constexpr (FORCE) {
