@@ -6,15 +6,18 @@
 // r < rc through a cell list rebuilt every step.
 //
 // Build (every step, every cluster independently, free boundaries):
-//   bbox    per chunk of 4096 atoms of a cluster: min/max, merged per
+//   bbox    per chunk of 1024 atoms of a cluster: min/max, merged per
 //           cluster with 64-bit integer atomics on an order-preserving
 //           encoding (exact, so the order does not matter);
 //   grid    per cluster: cells of edge h >= rc over the box (h grows beyond
 //           rc only if the box would need more cells than the cluster's cell
 //           capacity, so an escaping atom makes cells coarser, never wrong);
-//   count   per atom: its cell, integer atomics count atoms per cell;
-//   scan    exclusive prefix sum of the counts (one workgroup);
-//   scatter per atom: a slot in its cell (atomic cursor);
+//   count   per atom: its cell, integer atomics count atoms per cell (one
+//           atomic per cell and wavefront);
+//   scan    exclusive prefix sum of the counts (one workgroup), which clears
+//           the counts for the next build;
+//   scatter per atom: a slot in its cell (atomic cursor, again one atomic
+//           per cell and wavefront);
 //   order   per cell: every atom's slot becomes its rank by atom index, so
 //           the cell-sorted order is deterministic; positions are gathered.
 // Sweeps: one workgroup per cell; the candidates of the 27 neighbouring cells
@@ -76,7 +79,7 @@ hipError_t dalloc(T **p, size_t n) {
 // Build kernels
 // ---------------------------------------------------------------------------
 constexpr int kBBoxBlock = 256;
-constexpr int kBBoxChunk = 4096;  // atoms per bounding-box workgroup
+constexpr int kBBoxChunk = 1024;  // atoms per bounding-box workgroup
 
 // Doubles compared as signed 64-bit integers: flip the magnitude bits of
 // negative values (an involution, so the same map decodes).
@@ -89,39 +92,42 @@ __device__ __forceinline__ double ord_decode(long long b) {
 }
 
 // Partial bounding boxes: one workgroup per chunk of at most kBBoxChunk
-// atoms of one cluster; min/max are exact, so the atomic merge order does not
-// matter.
+// atoms of one cluster; min/max are exact, so neither the reduction order
+// nor the atomic merge order matters.
 __global__ __launch_bounds__(kBBoxBlock) void k_cell_bbox(const int4 *__restrict__ chunks,
                                                           const double4 *__restrict__ rp,
                                                           long long *__restrict__ box) {
-    __shared__ double sh[6][kBBoxBlock];
+    __shared__ double sh[6][kBBoxBlock / 64];
     const int4 ch = chunks[blockIdx.x];
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double m[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
     for (int i = ch.y + threadIdx.x; i < ch.z; i += kBBoxBlock) {
         const double4 q = rp[i];
-        lo[0] = fmin(lo[0], q.x);
-        lo[1] = fmin(lo[1], q.y);
-        lo[2] = fmin(lo[2], q.z);
-        hi[0] = fmax(hi[0], q.x);
-        hi[1] = fmax(hi[1], q.y);
-        hi[2] = fmax(hi[2], q.z);
+        m[0] = fmin(m[0], q.x);
+        m[1] = fmin(m[1], q.y);
+        m[2] = fmin(m[2], q.z);
+        m[3] = fmax(m[3], q.x);
+        m[4] = fmax(m[4], q.y);
+        m[5] = fmax(m[5], q.z);
     }
-    for (int d = 0; d < 3; ++d) {
-        sh[d][threadIdx.x] = lo[d];
-        sh[3 + d][threadIdx.x] = hi[d];
-    }
-    __syncthreads();
-    for (int s = kBBoxBlock / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            for (int d = 0; d < 3; ++d) {
-                sh[d][threadIdx.x] = fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + s]);
-                sh[3 + d][threadIdx.x] = fmax(sh[3 + d][threadIdx.x], sh[3 + d][threadIdx.x + s]);
-            }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            m[d] = fmin(m[d], __shfl_xor(m[d], o, 64));
+            m[3 + d] = fmax(m[3 + d], __shfl_xor(m[3 + d], o, 64));
         }
-        __syncthreads();
     }
-    if (threadIdx.x < 3) atomicMin(&box[6 * ch.x + threadIdx.x], ord_encode(sh[threadIdx.x][0]));
-    else if (threadIdx.x < 6) atomicMax(&box[6 * ch.x + threadIdx.x], ord_encode(sh[threadIdx.x][0]));
+    if (lane == 0)
+        for (int d = 0; d < 6; ++d) sh[d][w] = m[d];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int d = threadIdx.x;
+        double v = sh[d][0];
+        for (int k = 1; k < kBBoxBlock / 64; ++k) v = d < 3 ? fmin(v, sh[d][k]) : fmax(v, sh[d][k]);
+        if (d < 3) atomicMin(&box[6 * ch.x + d], ord_encode(v));
+        else atomicMax(&box[6 * ch.x + d], ord_encode(v));
+    }
 }
 
 // Reset the bounding-box accumulators (min slots to +inf, max slots to -inf).
@@ -184,55 +190,107 @@ __device__ __forceinline__ int cell_coord(double x, double o, double h, int n) {
     return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
 }
 
+// Lanes of a wavefront that land in the same cell share one atomic: the
+// lowest such lane (the leader) adds their number to ctr[cell] and every lane
+// of the group gets old value + its rank among them (by lane, i.e. by atom
+// index).  Lanes with cell < 0 take no part.  The groups are found first
+// (ballots only); then all leaders issue their atomics in one instruction, so
+// the wavefront waits for one round trip.  Consecutive atoms are mostly close,
+// so a wavefront touches few cells and the device-scope atomics drop
+// several-fold.
+template <bool RET>
+__device__ __forceinline__ int wave_cell_add(int *__restrict__ ctr, int cell, int lane) {
+    unsigned long long todo = __ballot(cell >= 0);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int leader = -1, rank = 0, size = 0;
+    while (todo) {
+        const int l = __builtin_ctzll(todo);
+        const int lc = __builtin_amdgcn_readlane(cell, l);
+        const unsigned long long same = __ballot(cell == lc);
+        if (cell == lc) {
+            leader = l;
+            rank = __popcll(same & below);
+            size = __popcll(same);
+        }
+        todo &= ~same;
+    }
+    if (!RET) {
+        if (cell >= 0 && rank == 0) atomicAdd(&ctr[cell], size);
+        return -1;
+    }
+    int base = 0;
+    if (cell >= 0 && rank == 0) base = atomicAdd(&ctr[cell], size);
+    base = __shfl(base, leader < 0 ? lane : leader, 64);
+    return cell >= 0 ? base + rank : -1;
+}
+
 __global__ __launch_bounds__(256) void k_cell_count(const CellGrid *__restrict__ grid,
                                                     const int *__restrict__ atom_cluster,
                                                     const double4 *__restrict__ rp, int *__restrict__ cell_of,
                                                     int *__restrict__ count, int natoms) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= natoms) return;
-    const CellGrid g = grid[atom_cluster[i]];
-    const double4 q = rp[i];
-    const int ix = cell_coord(q.x, g.ox, g.hx, g.nx);
-    const int iy = cell_coord(q.y, g.oy, g.hy, g.ny);
-    const int iz = cell_coord(q.z, g.oz, g.hz, g.nz);
-    const int cell = g.base + (iz * g.ny + iy) * g.nx + ix;
-    cell_of[i] = cell;
-    atomicAdd(&count[cell], 1);
+    int cell = -1;
+    if (i < natoms) {
+        const CellGrid g = grid[atom_cluster[i]];
+        const double4 q = rp[i];
+        const int ix = cell_coord(q.x, g.ox, g.hx, g.nx);
+        const int iy = cell_coord(q.y, g.oy, g.hy, g.ny);
+        const int iz = cell_coord(q.z, g.oz, g.hz, g.nz);
+        cell = g.base + (iz * g.ny + iy) * g.nx + ix;
+        cell_of[i] = cell;
+    }
+    (void)wave_cell_add<false>(count, cell, threadIdx.x & 63);
 }
 
 constexpr int kScanBlock = 1024;
 
-// Exclusive prefix sum of count[0..total) into start[0..total], one workgroup.
-__global__ __launch_bounds__(kScanBlock) void k_cell_scan(const int *__restrict__ count, int *__restrict__ start,
+// Exclusive prefix sum of count[0..total) into start[0..total] (and cursor),
+// one workgroup: per-thread chunk sums, wavefront scans, a scan of the
+// wavefront totals.  The counts are cleared behind the read, ready for the
+// next build's count pass.
+__global__ __launch_bounds__(kScanBlock) void k_cell_scan(int *__restrict__ count, int *__restrict__ start,
                                                           int *__restrict__ cursor, int total) {
-    __shared__ int sh[kScanBlock];
-    const int t = threadIdx.x;
+    __shared__ int wsum[kScanBlock / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int per = (total + kScanBlock - 1) / kScanBlock;
     const int a = min(total, t * per), b = min(total, a + per);
     int s = 0;
     for (int k = a; k < b; ++k) s += count[k];
-    sh[t] = s;
-    __syncthreads();
-    for (int d = 1; d < kScanBlock; d <<= 1) {  // inclusive Hillis-Steele scan of the chunk sums
-        const int v = t >= d ? sh[t - d] : 0;
-        __syncthreads();
-        sh[t] += v;
-        __syncthreads();
+    int x = s;  // inclusive scan over the wavefront
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
     }
-    int run = sh[t] - s;
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    if (w == 0) {
+        int v = lane < kScanBlock / 64 ? wsum[lane] : 0;
+#pragma unroll
+        for (int d = 1; d < kScanBlock / 64; d <<= 1) {
+            const int y = __shfl_up(v, d, 64);
+            if (lane >= d) v += y;
+        }
+        if (lane < kScanBlock / 64) wsum[lane] = v;
+    }
+    __syncthreads();
+    int run = x - s + (w > 0 ? wsum[w - 1] : 0);
     for (int k = a; k < b; ++k) {
+        const int c = count[k];
         start[k] = run;
         cursor[k] = run;
-        run += count[k];
+        count[k] = 0;
+        run += c;
     }
-    if (t == kScanBlock - 1) start[total] = sh[t];
+    if (t == kScanBlock - 1) start[total] = wsum[kScanBlock / 64 - 1];
 }
 
 __global__ __launch_bounds__(256) void k_cell_scatter(const int *__restrict__ cell_of, int *__restrict__ cursor,
                                                       int *__restrict__ perm, int natoms) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= natoms) return;
-    perm[atomicAdd(&cursor[cell_of[i]], 1)] = i;
+    const int cell = i < natoms ? cell_of[i] : -1;
+    const int slot = wave_cell_add<true>(cursor, cell, threadIdx.x & 63);
+    if (i < natoms) perm[slot] = i;
 }
 
 // One wavefront per cell: the slot of each atom is its rank (the number of
@@ -494,6 +552,8 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
         (e = hipMemcpy(cl->chunks, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice)) != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_cell_box_reset, dim3((6 * nclusters + 63) / 64), dim3(64), 0, 0, cl->box, nclusters);
+    // the counts start at zero; each build's scan clears them again
+    if (base > 0) hipLaunchKernelGGL(k_cell_clear, dim3((base + 255) / 256), dim3(256), 0, 0, cl->count, base);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
     if ((e = dalloc(&cl->pslot, natoms)) != hipSuccess) return e;
@@ -520,7 +580,6 @@ hipError_t cell_list_build(CellList *cl, const double4 *rp, hipStream_t s) {
         hipLaunchKernelGGL(k_cell_bbox, dim3(cl->nchunks), dim3(kBBoxBlock), 0, s, cl->chunks, rp, cl->box);
     hipLaunchKernelGGL(k_cell_grid, dim3((cl->nclusters + 63) / 64), dim3(64), 0, s, cl->grid, cl->box, cl->nclusters,
                        cl->rc);
-    hipLaunchKernelGGL(k_cell_clear, dim3((tc + 255) / 256), dim3(256), 0, s, cl->count, tc);
     if (na > 0)
         hipLaunchKernelGGL(k_cell_count, dim3((na + 255) / 256), dim3(256), 0, s, cl->grid, cl->atom_cluster, rp,
                            cl->cell_of, cl->count, na);
