@@ -343,8 +343,10 @@ __global__ __launch_bounds__(256) void k_cell_gather_p(const int *__restrict__ s
 // in the own row at one known candidate index (the self pair).
 // Neighbourhoods larger than the LDS buffer (only when cells coarsened after
 // an atom escaped) read the same candidates from global memory.
-constexpr int kCellWaves = 8;
-constexpr int kCellStage = 2000;  // staged candidates (62.5 KiB: two workgroups per CU)
+constexpr int kCellWaves = 16;
+constexpr int kCellStage = 2048;  // staged candidates (64 KiB: two workgroups per CU)
+constexpr int kCellQueue = 128;   // in-range candidates queued per wavefront (< 64 left + 64 new)
+constexpr bool kCellCompact[2] = {true, true};  // density, force sweep
 
 template <int PREC, bool GEN, bool FORCE>
 __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *__restrict__ grid,
@@ -356,8 +358,13 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
                                                                 double *__restrict__ part, int tile_shift,
                                                                 PotConst pc) {
     constexpr int Q = FORCE ? 4 : 1;
-    extern __shared__ double4 lj[];
+    // staged candidates as four arrays (x, y, z, w): lanes reading
+    // consecutive candidates touch consecutive 8-byte words, conflict-free
+    extern __shared__ double lds_c[];
+    double *const lx = lds_c, *const ly = lds_c + kCellStage, *const lz = lds_c + 2 * kCellStage,
+                  *const lw = lds_c + 3 * kCellStage;
     __shared__ int seg_lo[9], seg_len[9], seg_off[10];
+    __shared__ int queue[kCellWaves][kCellQueue];
     const int cell = blockIdx.x;
     const CellGrid g = grid[cell_cluster[cell]];
     const int local = cell - g.base;
@@ -383,8 +390,9 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
         for (int r = 0; r < 9; ++r) seg_off[r + 1] = seg_off[r] + seg_len[r];
     }
     __syncthreads();
-    const int M = seg_off[9];
-    const bool staged = M <= kCellStage;
+    const int M = __builtin_amdgcn_readfirstlane(seg_off[9]);
+    const int M64 = (M + 63) & ~63;  // candidates padded to whole wavefronts
+    const bool staged = M64 <= kCellStage;
     // sorted atom of candidate p (p < M)
     auto cand = [&](int p) {
         int r = 0;
@@ -392,7 +400,20 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
         return seg_lo[r] + (p - seg_off[r]);
     };
     if (staged) {
-        for (int p = tid; p < M; p += 64 * kCellWaves) lj[p] = rs[cand(p)];
+        for (int p = tid; p < M; p += 64 * kCellWaves) {
+            const double4 q = rs[cand(p)];
+            lx[p] = q.x;
+            ly[p] = q.y;
+            lz[p] = q.z;
+            lw[p] = q.w;
+        }
+        // padding: far away, so r^2 is +inf and never within rc
+        for (int p = M + tid; p < M64; p += 64 * kCellWaves) {
+            lx[p] = 1.0e300;
+            ly[p] = 1.0e300;
+            lz[p] = 1.0e300;
+            lw[p] = 0.0;
+        }
     }
     __syncthreads();
     const int tile = 1 << tile_shift;
@@ -409,14 +430,52 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
         double acc[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) acc[q] = 0.0;
-#pragma unroll 2
-        for (int p = lane; p < M; p += 64) {
-            const double4 q = staged ? lj[p] : rs[cand(p)];
+        // the pair terms of one candidate (self or void when `off`)
+        auto staged_cand = [&](int p) { return make_double4(lx[p], ly[p], lz[p], lw[p]); };
+        auto pair_terms = [&](const double4 &q, bool off) {
             if constexpr (FORCE)
-                force_pair<PREC, GEN, true, true>(qi.x - q.x, qi.y - q.y, qi.z - q.z, p == self_p, c_i, q.w, cif,
+                force_pair<PREC, GEN, true, true>(qi.x - q.x, qi.y - q.y, qi.z - q.z, off, c_i, q.w, cif,
                                                   (float)q.w, acc[0], acc[1], acc[2], acc[3], pc, Af);
             else
-                density_pair<PREC, GEN, true, true>(qi.x - q.x, qi.y - q.y, qi.z - q.z, p == self_p, acc[0], pc);
+                density_pair<PREC, GEN, true, true>(qi.x - q.x, qi.y - q.y, qi.z - q.z, off, acc[0], pc);
+        };
+        if (staged && kCellCompact[FORCE]) {
+            // Only about a fifth of the candidates lie within rc.  A first pass
+            // tests r^2 < rc^2 and queues the hits (ring buffer per
+            // wavefront); every 64 queued hits make one pass of the pair
+            // terms with all lanes busy.  The test is the pair terms' own
+            // cutoff expression, so no pair changes side.
+            int *qu = queue[wave];
+            int head = 0, qn = 0;  // wavefront-uniform
+            for (int base = 0; base < M64; base += 64) {
+                const int p = base + lane;
+                const double dx = qi.x - lx[p], dy = qi.y - ly[p], dz = qi.z - lz[p];
+                const bool in =
+                    (__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)) < pc.rc2) & (lane != self_p - base);
+                const unsigned long long hit = __ballot(in);
+                const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(hit >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((unsigned)hit, 0u));
+                if (in) qu[(head + qn + rank) & (kCellQueue - 1)] = p;
+                qn += __popcll(hit);
+                if (qn >= 64) {
+                    __builtin_amdgcn_wave_barrier();
+                    const int e = qu[(head + lane) & (kCellQueue - 1)];
+                    head = (head + 64) & (kCellQueue - 1);
+                    qn -= 64;
+                    pair_terms(staged_cand(e), false);
+                }
+            }
+            if (qn > 0) {
+                __builtin_amdgcn_wave_barrier();
+                const bool v = lane < qn;
+                // lanes past the queue read candidate 0 (valid: the own cell
+                // is not empty) and add nothing
+                const int e = v ? qu[(head + lane) & (kCellQueue - 1)] : 0;
+                pair_terms(staged_cand(e), !v);
+            }
+        } else {
+#pragma unroll 2
+            for (int p = lane; p < M; p += 64) pair_terms(staged ? staged_cand(p) : rs[cand(p)], p == self_p);
         }
         if constexpr (FORCE) unscale_force<PREC, GEN>(acc[0], acc[1], acc[2], acc[3]);
 #pragma unroll
