@@ -62,6 +62,8 @@ struct CellList {
     int *pslot = nullptr;         // atom -> partial index (tile * TILE + li)
     int *atom_cluster = nullptr;  // [natoms]
     double4 *rs = nullptr;        // sorted positions (+ P for the force sweep)
+    uint16_t *nbr = nullptr;      // [natoms * kCellNbrCap] per sorted atom: staged candidates within rc
+    int *nbr_n = nullptr;         // [natoms] number of such candidates (written by the density sweep)
 };
 
 namespace {
@@ -346,7 +348,7 @@ __global__ __launch_bounds__(256) void k_cell_gather_p(const int *__restrict__ s
 constexpr int kCellWaves = 16;
 constexpr int kCellStage = 2048;  // staged candidates (64 KiB: two workgroups per CU)
 constexpr int kCellQueue = 128;   // in-range candidates queued per wavefront (< 64 left + 64 new)
-constexpr bool kCellCompact[2] = {true, true};  // density, force sweep
+constexpr int kCellNbrCap = 512;  // listed candidates within rc per atom (an atom with more re-tests)
 
 template <int PREC, bool GEN, bool FORCE>
 __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *__restrict__ grid,
@@ -356,7 +358,8 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
                                                                 const int *__restrict__ sperm,
                                                                 const int *__restrict__ pslot,
                                                                 double *__restrict__ part, int tile_shift,
-                                                                PotConst pc) {
+                                                                uint16_t *__restrict__ nbr,
+                                                                int *__restrict__ nbr_n, PotConst pc) {
     constexpr int Q = FORCE ? 4 : 1;
     // staged candidates as four arrays (x, y, z, w): lanes reading
     // consecutive candidates touch consecutive 8-byte words, conflict-free
@@ -439,14 +442,27 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
             else
                 density_pair<PREC, GEN, true, true>(qi.x - q.x, qi.y - q.y, qi.z - q.z, off, acc[0], pc);
         };
-        if (staged && kCellCompact[FORCE]) {
+        uint16_t *const list = nbr + (size_t)k * kCellNbrCap;
+        const int listed = FORCE && staged ? __builtin_amdgcn_readfirstlane(nbr_n[k]) : -1;
+        if (FORCE && staged && listed <= kCellNbrCap) {
+            // the density sweep of this step listed the candidates within rc
+            // (same cell list, same positions); lanes take the entries in the
+            // order the queue below hands them out
+            for (int base = 0; base < listed; base += 64) {
+                const bool v = base + lane < listed;
+                const int e = list[v ? base + lane : base];  // in bounds for every lane
+                pair_terms(staged_cand(v ? e : 0), !v);
+            }
+        } else if (staged) {
             // Only about a fifth of the candidates lie within rc.  A first pass
             // tests r^2 < rc^2 and queues the hits (ring buffer per
             // wavefront); every 64 queued hits make one pass of the pair
             // terms with all lanes busy.  The test is the pair terms' own
-            // cutoff expression, so no pair changes side.
+            // cutoff expression, so no pair changes side.  The density sweep
+            // also stores the hits as they leave the queue (up to kCellNbrCap
+            // per atom, one coalesced store per 64) for the force sweep.
             int *qu = queue[wave];
-            int head = 0, qn = 0;  // wavefront-uniform
+            int head = 0, qn = 0, total = 0;  // wavefront-uniform
             for (int base = 0; base < M64; base += 64) {
                 const int p = base + lane;
                 const double dx = qi.x - lx[p], dy = qi.y - ly[p], dz = qi.z - lz[p];
@@ -462,6 +478,8 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
                     const int e = qu[(head + lane) & (kCellQueue - 1)];
                     head = (head + 64) & (kCellQueue - 1);
                     qn -= 64;
+                    if (!FORCE && total + 64 <= kCellNbrCap) list[total + lane] = (uint16_t)e;
+                    total += 64;
                     pair_terms(staged_cand(e), false);
                 }
             }
@@ -471,8 +489,11 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
                 // lanes past the queue read candidate 0 (valid: the own cell
                 // is not empty) and add nothing
                 const int e = v ? qu[(head + lane) & (kCellQueue - 1)] : 0;
+                if (!FORCE && v && total + lane < kCellNbrCap) list[total + lane] = (uint16_t)e;
+                total += qn;
                 pair_terms(staged_cand(e), !v);
             }
+            if (!FORCE && lane == 0) nbr_n[k] = total;
         } else {
 #pragma unroll 2
             for (int p = lane; p < M; p += 64) pair_terms(staged ? staged_cand(p) : rs[cand(p)], p == self_p);
@@ -501,7 +522,8 @@ hipError_t launch_cell_sweep(CellList *cl, double *part, const PotConst &pc, int
     (void)hipGetLastError();
     const dim3 grid(cl->total_cap), block(64 * kCellWaves);
     const size_t lds = kCellStage * sizeof(double4);
-#define SCMD_CELL_ARGS cl->grid, cl->cell_cluster, cl->start, cl->rs, cl->sperm, cl->pslot, part, cl->tile_shift, pc
+#define SCMD_CELL_ARGS \
+    cl->grid, cl->cell_cluster, cl->start, cl->rs, cl->sperm, cl->pslot, part, cl->tile_shift, cl->nbr, cl->nbr_n, pc
     if (precision == SCMD_FP64) {
         if (pc.generic)
             hipLaunchKernelGGL((k_cell_sweep<SCMD_FP64, true, FORCE>), grid, block, lds, s, SCMD_CELL_ARGS);
@@ -531,8 +553,9 @@ CellList *cell_list_create() {
 
 void cell_list_destroy(CellList *cl) {
     if (!cl) return;
-    void *ptrs[] = {cl->grid,  cl->cell_cluster, cl->count, cl->start,        cl->cursor, cl->cell_of, cl->perm,
-                    cl->sperm, cl->box,          cl->chunks, cl->pslot, cl->atom_cluster, cl->rs};
+    void *ptrs[] = {cl->grid,  cl->cell_cluster, cl->count,  cl->start, cl->cursor,       cl->cell_of, cl->perm,
+                    cl->sperm, cl->box,          cl->chunks, cl->pslot, cl->atom_cluster, cl->rs,      cl->nbr,
+                    cl->nbr_n};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete cl;
@@ -618,6 +641,8 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
     if ((e = dalloc(&cl->pslot, natoms)) != hipSuccess) return e;
     if ((e = dalloc(&cl->atom_cluster, natoms)) != hipSuccess) return e;
     if ((e = dalloc(&cl->rs, natoms)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->nbr, (size_t)natoms * kCellNbrCap)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->nbr_n, natoms)) != hipSuccess) return e;
     if ((e = hipMemcpy(cl->grid, grids.data(), nclusters * sizeof(CellGrid), hipMemcpyHostToDevice)) != hipSuccess)
         return e;
     if (base > 0 &&

@@ -351,6 +351,15 @@ def test_cell_list_compute_parity(n, precision):
     check_single(pos, precision=precision, params=dict(rc=RC))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cell_list_crowded_neighbourhoods(precision):
+    # rc = 16 A over a 600-atom cluster (about 21 A across): 193 atoms have
+    # more neighbours within rc than the per-atom list of the density sweep
+    # holds (512), so the force sweep re-tests their candidates while the
+    # others read their lists
+    check_single(_cluster(600, seed=600, amp=0.2), precision=precision, params=dict(rc=16.0))
+
+
 def test_cell_list_batch_with_escaped_atom():
     # an atom that leaves its cluster after the grid was planned stretches the
     # box beyond the cell capacity: cells coarsen, results stay exact
