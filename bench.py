@@ -12,7 +12,8 @@ spherical fcc Ni cut (R = 18 A), +-0.05 A jitter, Maxwell-Boltzmann start at
 FP64.  Prints one JSON line:
 
   value        whole-job atom-steps/s over exactly K timed steps
-  roofline     the force sweep (dominant kernel): algorithmic FLOP per launch
+  roofline     the force sweep (dominant kernel; on the cell list the longer
+               of the two sweeps): algorithmic FLOP per launch
                (30 FLOP per unordered pair: a step without the pair-energy
                term, like all but the last step of each 32-step graph) / its
                device time per launch,
@@ -138,13 +139,22 @@ def time_gpu(w, steps: int, warmup: int, tuning=None):
         res["pairs_within_rc"] = pairs_rc
     res["pair_interactions_per_s"] = pairs * steps / dt
     res["pairs_per_step"] = pairs
+    # the roofline is that of the longer sweep (the force sweep, except on
+    # the cell list, where the density sweep also finds the pairs within rc);
+    # the other sweep's figures go beside it
+    sweeps = []
     if f_ms > 0:
-        ach = FLOP_FORCE_PER_PAIR * pairs / (f_ms * 1e-3) / 1e12
-        res["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                           "frac": ach / PEAK_FP64_TFLOPS, "traffic": None}
+        sweeps.append(("force sweep", f_ms, FLOP_FORCE_PER_PAIR * pairs / (f_ms * 1e-3) / 1e12))
     if d_ms > 0:
-        ach_d = FLOP_DENSITY_PER_PAIR * pairs / (d_ms * 1e-3) / 1e12
-        res["density_roofline"] = {"achieved": ach_d, "frac": ach_d / PEAK_FP64_TFLOPS}
+        sweeps.append(("density sweep", d_ms, FLOP_DENSITY_PER_PAIR * pairs / (d_ms * 1e-3) / 1e12))
+    sweeps.sort(key=lambda x: -x[1])
+    if sweeps:
+        name, _, ach = sweeps[0]
+        res["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                           "frac": ach / PEAK_FP64_TFLOPS, "traffic": None, "kernel": name}
+    if len(sweeps) > 1:
+        name, _, ach = sweeps[1]
+        res["other_sweep_roofline"] = {"kernel": name, "achieved": ach, "frac": ach / PEAK_FP64_TFLOPS}
     return res
 
 
@@ -204,7 +214,8 @@ def main(argv=None):
     print(f"[bench] {w.name}: {w.n_atoms} atoms, {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
           flush=True)
     main_res = time_gpu(w, args.steps, args.warmup, tuning=json.loads(args.tuning) if args.tuning else None)
-    if main_res.get("roofline") is not None:
+    # the committed counters are those of force-sweep kernels
+    if main_res.get("roofline") is not None and main_res["roofline"]["kernel"] == "force sweep":
         main_res["roofline"]["traffic"] = measured_traffic(args.workload)
     print(f"[bench] {main_res['atom_steps_per_s']:.4e} atom-steps/s, {main_res['ms_per_step']:.4f} ms/step",
           file=sys.stderr, flush=True)

@@ -9,13 +9,13 @@
 //   bbox    per chunk of 1024 atoms of a cluster: min/max, merged per
 //           cluster with 64-bit integer atomics on an order-preserving
 //           encoding (exact, so the order does not matter);
-//   grid    per cluster: cells of edge h >= rc over the box (h grows beyond
-//           rc only if the box would need more cells than the cluster's cell
-//           capacity, so an escaping atom makes cells coarser, never wrong);
-//   count   per atom: its cell, integer atomics count atoms per cell (one
-//           atomic per cell and wavefront);
+//   count   per atom: the grid of its cluster, cells of edge h >= rc over
+//           the box (h grows beyond rc only if the box would need more cells
+//           than the cluster's cell capacity, so an escaping atom makes cells
+//           coarser, never wrong); its cell; integer atomics count atoms per
+//           cell (one atomic per cell and wavefront);
 //   scan    exclusive prefix sum of the counts (one workgroup), which clears
-//           the counts for the next build;
+//           the counts and resets the boxes for the next build;
 //   scatter per atom: a slot in its cell (atomic cursor, again one atomic
 //           per cell and wavefront);
 //   order   per cell: every atom's slot becomes its rank by atom index, so
@@ -48,7 +48,8 @@ struct CellGrid {
 struct CellList {
     int nclusters = 0, natoms = 0, total_cap = 0, tile = 0, tile_shift = 0;
     double rc = 0.0;
-    CellGrid *grid = nullptr;
+    CellGrid *grid = nullptr;     // [nclusters] this step's grids
+    CellGrid *grid0 = nullptr;    // [nclusters] fixed fields (capacity, base, atoms)
     int *cell_cluster = nullptr;  // [total_cap]
     int *count = nullptr;         // [total_cap]
     int *start = nullptr;         // [total_cap + 1]
@@ -61,7 +62,8 @@ struct CellList {
     int nchunks = 0;
     int *pslot = nullptr;         // atom -> partial index (tile * TILE + li)
     int *atom_cluster = nullptr;  // [natoms]
-    double4 *rs = nullptr;        // sorted positions (+ P for the force sweep)
+    double4 *rs = nullptr;        // sorted positions (density sweep; the force sweep reads P with them
+                                  // from the density finish through sperm)
     uint16_t *nbr = nullptr;      // [natoms * kCellNbrCap] per sorted atom: staged candidates within rc
     int *nbr_n = nullptr;         // [natoms] number of such candidates (written by the density sweep)
 };
@@ -139,18 +141,15 @@ __global__ __launch_bounds__(64) void k_cell_box_reset(long long *__restrict__ b
     box[k] = ord_encode((k % 6) < 3 ? INFINITY : -INFINITY);
 }
 
-// One thread per cluster: cells of edge >= rc over the box (h grows beyond rc
-// only when the box needs more cells than the capacity), then reset the box.
-__global__ __launch_bounds__(64) void k_cell_grid(CellGrid *__restrict__ grid, long long *__restrict__ box,
-                                                  int nclusters, double rc) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nclusters) return;
-    CellGrid g = grid[c];
+// Cells of edge >= rc over a cluster's bounding box (h grows beyond rc only
+// when the box needs more cells than the capacity).  g holds the fixed fields
+// (capacity, base, atoms); the result adds origin, edges and cell counts.
+__device__ __forceinline__ CellGrid grid_from_box(CellGrid g, const long long *__restrict__ b, double rc) {
     const int cap[3] = {g.cx, g.cy, g.cz};
     double o[3], h[3];
     int n[3];
     for (int d = 0; d < 3; ++d) {
-        const double lo = ord_decode(box[6 * c + d]), hi = ord_decode(box[6 * c + 3 + d]);
+        const double lo = ord_decode(b[d]), hi = ord_decode(b[3 + d]);
         const double ext = g.n > 0 ? hi - lo : 0.0;
         o[d] = g.n > 0 ? lo : 0.0;
         const double want = floor(ext / rc) + 1.0;
@@ -166,8 +165,6 @@ __global__ __launch_bounds__(64) void k_cell_grid(CellGrid *__restrict__ grid, l
             n[d] = (int)want;
             h[d] = rc;
         }
-        box[6 * c + d] = ord_encode(INFINITY);
-        box[6 * c + 3 + d] = ord_encode(-INFINITY);
     }
     g.ox = o[0];
     g.oy = o[1];
@@ -178,7 +175,7 @@ __global__ __launch_bounds__(64) void k_cell_grid(CellGrid *__restrict__ grid, l
     g.nx = n[0];
     g.ny = n[1];
     g.nz = n[2];
-    grid[c] = g;
+    return g;
 }
 
 __global__ __launch_bounds__(256) void k_cell_clear(int *__restrict__ count, int total) {
@@ -226,14 +223,20 @@ __device__ __forceinline__ int wave_cell_add(int *__restrict__ ctr, int cell, in
     return cell >= 0 ? base + rank : -1;
 }
 
-__global__ __launch_bounds__(256) void k_cell_count(const CellGrid *__restrict__ grid,
+// Per atom: the grid of its cluster from this step's bounding box (every
+// thread of a cluster computes the same grid; the cluster's first atom stores
+// it for the sweeps), its cell, and the per-cell counts.
+__global__ __launch_bounds__(256) void k_cell_count(const CellGrid *__restrict__ grid0, CellGrid *__restrict__ grid,
+                                                    const long long *__restrict__ box, double rc,
                                                     const int *__restrict__ atom_cluster,
                                                     const double4 *__restrict__ rp, int *__restrict__ cell_of,
                                                     int *__restrict__ count, int natoms) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     int cell = -1;
     if (i < natoms) {
-        const CellGrid g = grid[atom_cluster[i]];
+        const int c = atom_cluster[i];
+        const CellGrid g = grid_from_box(grid0[c], box + 6 * c, rc);
+        if (i == g.off) grid[c] = g;
         const double4 q = rp[i];
         const int ix = cell_coord(q.x, g.ox, g.hx, g.nx);
         const int iy = cell_coord(q.y, g.oy, g.hy, g.ny);
@@ -248,10 +251,11 @@ constexpr int kScanBlock = 1024;
 
 // Exclusive prefix sum of count[0..total) into start[0..total] (and cursor),
 // one workgroup: per-thread chunk sums, wavefront scans, a scan of the
-// wavefront totals.  The counts are cleared behind the read, ready for the
-// next build's count pass.
+// wavefront totals.  The counts are cleared behind the read and the bounding
+// boxes reset, ready for the next build.
 __global__ __launch_bounds__(kScanBlock) void k_cell_scan(int *__restrict__ count, int *__restrict__ start,
-                                                          int *__restrict__ cursor, int total) {
+                                                          int *__restrict__ cursor, int total,
+                                                          long long *__restrict__ box, int nclusters) {
     __shared__ int wsum[kScanBlock / 64];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int per = (total + kScanBlock - 1) / kScanBlock;
@@ -285,6 +289,7 @@ __global__ __launch_bounds__(kScanBlock) void k_cell_scan(int *__restrict__ coun
         run += c;
     }
     if (t == kScanBlock - 1) start[total] = wsum[kScanBlock / 64 - 1];
+    for (int k = t; k < 6 * nclusters; k += kScanBlock) box[k] = ord_encode((k % 6) < 3 ? INFINITY : -INFINITY);
 }
 
 __global__ __launch_bounds__(256) void k_cell_scatter(const int *__restrict__ cell_of, int *__restrict__ cursor,
@@ -324,14 +329,6 @@ __global__ __launch_bounds__(64) void k_cell_order(const int *__restrict__ start
     }
 }
 
-// rs[k].w = P of atom perm[k] (after the density sweep has been finished).
-__global__ __launch_bounds__(256) void k_cell_gather_p(const int *__restrict__ sperm, const double4 *__restrict__ xp,
-                                                       double4 *__restrict__ rs, int natoms) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= natoms) return;
-    rs[k] = xp[sperm[k]];
-}
-
 // ---------------------------------------------------------------------------
 // Sweeps
 // ---------------------------------------------------------------------------
@@ -359,7 +356,8 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
                                                                 const int *__restrict__ pslot,
                                                                 double *__restrict__ part, int tile_shift,
                                                                 uint16_t *__restrict__ nbr,
-                                                                int *__restrict__ nbr_n, PotConst pc) {
+                                                                int *__restrict__ nbr_n,
+                                                                const double4 *__restrict__ xp, PotConst pc) {
     constexpr int Q = FORCE ? 4 : 1;
     // staged candidates as four arrays (x, y, z, w): lanes reading
     // consecutive candidates touch consecutive 8-byte words, conflict-free
@@ -402,9 +400,12 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
         while (p >= seg_off[r + 1]) ++r;
         return seg_lo[r] + (p - seg_off[r]);
     };
+    // the record of sorted atom k: position (density sweep), position and P
+    // from the density sweep's finish (force sweep)
+    auto rec = [&](int k) { return FORCE ? xp[sperm[k]] : rs[k]; };
     if (staged) {
         for (int p = tid; p < M; p += 64 * kCellWaves) {
-            const double4 q = rs[cand(p)];
+            const double4 q = rec(cand(p));
             lx[p] = q.x;
             ly[p] = q.y;
             lz[p] = q.z;
@@ -426,7 +427,7 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
     const int self0 = seg_off[4] - seg_lo[4];
     for (int a = wave; a < cnt; a += kCellWaves) {
         const int k = s0 + a;
-        const double4 qi = rs[k];
+        const double4 qi = rec(k);
         const double c_i = -qi.w;
         const float cif = (float)c_i;
         const int self_p = self0 + k;
@@ -496,7 +497,7 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
             if (!FORCE && lane == 0) nbr_n[k] = total;
         } else {
 #pragma unroll 2
-            for (int p = lane; p < M; p += 64) pair_terms(staged ? staged_cand(p) : rs[cand(p)], p == self_p);
+            for (int p = lane; p < M; p += 64) pair_terms(staged ? staged_cand(p) : rec(cand(p)), p == self_p);
         }
         if constexpr (FORCE) unscale_force<PREC, GEN>(acc[0], acc[1], acc[2], acc[3]);
 #pragma unroll
@@ -518,12 +519,13 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
 }
 
 template <bool FORCE>
-hipError_t launch_cell_sweep(CellList *cl, double *part, const PotConst &pc, int precision, hipStream_t s) {
+hipError_t launch_cell_sweep(CellList *cl, double *part, const double4 *xp, const PotConst &pc, int precision,
+                             hipStream_t s) {
     (void)hipGetLastError();
     const dim3 grid(cl->total_cap), block(64 * kCellWaves);
     const size_t lds = kCellStage * sizeof(double4);
 #define SCMD_CELL_ARGS \
-    cl->grid, cl->cell_cluster, cl->start, cl->rs, cl->sperm, cl->pslot, part, cl->tile_shift, cl->nbr, cl->nbr_n, pc
+    cl->grid, cl->cell_cluster, cl->start, cl->rs, cl->sperm, cl->pslot, part, cl->tile_shift, cl->nbr, cl->nbr_n, xp, pc
     if (precision == SCMD_FP64) {
         if (pc.generic)
             hipLaunchKernelGGL((k_cell_sweep<SCMD_FP64, true, FORCE>), grid, block, lds, s, SCMD_CELL_ARGS);
@@ -553,9 +555,9 @@ CellList *cell_list_create() {
 
 void cell_list_destroy(CellList *cl) {
     if (!cl) return;
-    void *ptrs[] = {cl->grid,  cl->cell_cluster, cl->count,  cl->start, cl->cursor,       cl->cell_of, cl->perm,
-                    cl->sperm, cl->box,          cl->chunks, cl->pslot, cl->atom_cluster, cl->rs,      cl->nbr,
-                    cl->nbr_n};
+    void *ptrs[] = {cl->grid0, cl->grid,  cl->cell_cluster, cl->count,        cl->start, cl->cursor, cl->cell_of,
+                    cl->perm,  cl->sperm, cl->box,          cl->chunks,       cl->pslot, cl->atom_cluster,
+                    cl->rs,    cl->nbr,   cl->nbr_n};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete cl;
@@ -621,6 +623,7 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
             ac[tiles[t].i0 + li] = tiles[t].c;
         }
     if ((e = dalloc(&cl->grid, nclusters)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->grid0, nclusters)) != hipSuccess) return e;
     if ((e = dalloc(&cl->cell_cluster, base)) != hipSuccess) return e;
     if ((e = dalloc(&cl->count, base)) != hipSuccess) return e;
     if ((e = dalloc(&cl->start, base + 1)) != hipSuccess) return e;
@@ -645,6 +648,8 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
     if ((e = dalloc(&cl->nbr_n, natoms)) != hipSuccess) return e;
     if ((e = hipMemcpy(cl->grid, grids.data(), nclusters * sizeof(CellGrid), hipMemcpyHostToDevice)) != hipSuccess)
         return e;
+    if ((e = hipMemcpy(cl->grid0, grids.data(), nclusters * sizeof(CellGrid), hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
     if (base > 0 &&
         (e = hipMemcpy(cl->cell_cluster, cell_cluster.data(), base * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
         return e;
@@ -662,12 +667,11 @@ hipError_t cell_list_build(CellList *cl, const double4 *rp, hipStream_t s) {
     const int na = cl->natoms, tc = cl->total_cap;
     if (cl->nchunks > 0)
         hipLaunchKernelGGL(k_cell_bbox, dim3(cl->nchunks), dim3(kBBoxBlock), 0, s, cl->chunks, rp, cl->box);
-    hipLaunchKernelGGL(k_cell_grid, dim3((cl->nclusters + 63) / 64), dim3(64), 0, s, cl->grid, cl->box, cl->nclusters,
-                       cl->rc);
     if (na > 0)
-        hipLaunchKernelGGL(k_cell_count, dim3((na + 255) / 256), dim3(256), 0, s, cl->grid, cl->atom_cluster, rp,
-                           cl->cell_of, cl->count, na);
-    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(kScanBlock), 0, s, cl->count, cl->start, cl->cursor, tc);
+        hipLaunchKernelGGL(k_cell_count, dim3((na + 255) / 256), dim3(256), 0, s, cl->grid0, cl->grid, cl->box, cl->rc,
+                           cl->atom_cluster, rp, cl->cell_of, cl->count, na);
+    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(kScanBlock), 0, s, cl->count, cl->start, cl->cursor, tc, cl->box,
+                       cl->nclusters);
     if (na > 0)
         hipLaunchKernelGGL(k_cell_scatter, dim3((na + 255) / 256), dim3(256), 0, s, cl->cell_of, cl->cursor, cl->perm,
                            na);
@@ -677,20 +681,14 @@ hipError_t cell_list_build(CellList *cl, const double4 *rp, hipStream_t s) {
 
 hipError_t cell_list_density(CellList *cl, const SweepBuffers &B, const ITile *tiles, int ntiles, int tile,
                              const PotConst &pc, int precision, hipStream_t s) {
-    hipError_t e = launch_cell_sweep<false>(cl, B.part, pc, precision, s);
+    hipError_t e = launch_cell_sweep<false>(cl, B.part, nullptr, pc, precision, s);
     if (e != hipSuccess) return e;
     return launch_density_reduce(tiles, ntiles, tile, B, pc, 1, s);
 }
 
 hipError_t cell_list_force(CellList *cl, const SweepBuffers &B, const StepArgs &a, const ITile *tiles, int ntiles,
                            int tile, const PotConst &pc, int precision, hipStream_t s) {
-    (void)hipGetLastError();
-    if (cl->natoms > 0)
-        hipLaunchKernelGGL(k_cell_gather_p, dim3((cl->natoms + 255) / 256), dim3(256), 0, s, cl->sperm, B.xp, cl->rs,
-                           cl->natoms);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    e = launch_cell_sweep<true>(cl, B.part, pc, precision, s);
+    hipError_t e = launch_cell_sweep<true>(cl, B.part, B.xp, pc, precision, s);
     if (e != hipSuccess) return e;
     return launch_force_reduce(tiles, ntiles, tile, B, a, pc, 1, s);
 }
