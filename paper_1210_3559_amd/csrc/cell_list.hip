@@ -54,6 +54,7 @@ struct CellList {
     int *count = nullptr;         // [total_cap]
     int *start = nullptr;         // [total_cap + 1]
     int *cursor = nullptr;        // [total_cap]
+    int *corder = nullptr;        // [total_cap] cells in the order the sweeps take them (fullest first)
     int *cell_of = nullptr;       // [natoms]
     int *perm = nullptr;          // cell slot -> atom, as scattered
     int *sperm = nullptr;         // cell slot -> atom, sorted by atom index within each cell
@@ -249,15 +250,23 @@ __global__ __launch_bounds__(256) void k_cell_count(const CellGrid *__restrict__
 
 constexpr int kScanBlock = 1024;
 
+constexpr int kOrderBins = 256;
+
 // Exclusive prefix sum of count[0..total) into start[0..total] (and cursor),
 // one workgroup: per-thread chunk sums, wavefront scans, a scan of the
-// wavefront totals.  The counts are cleared behind the read and the bounding
-// boxes reset, ready for the next build.
+// wavefront totals.  Also the order in which the sweeps take the cells:
+// fullest first (a counting sort on the atom count, clamped at 255), so that
+// the longest workgroups start first and the short ones fill in behind them
+// (the order within one count depends on timing; each cell's sums do not
+// depend on which workgroup takes it).  The counts are cleared behind the
+// read and the bounding boxes reset, ready for the next build.
 __global__ __launch_bounds__(kScanBlock) void k_cell_scan(int *__restrict__ count, int *__restrict__ start,
-                                                          int *__restrict__ cursor, int total,
-                                                          long long *__restrict__ box, int nclusters) {
+                                                          int *__restrict__ cursor, int *__restrict__ corder,
+                                                          int total, long long *__restrict__ box, int nclusters) {
     __shared__ int wsum[kScanBlock / 64];
+    __shared__ int bins[kOrderBins];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    for (int q = t; q < kOrderBins; q += kScanBlock) bins[q] = 0;
     const int per = (total + kScanBlock - 1) / kScanBlock;
     const int a = min(total, t * per), b = min(total, a + per);
     int s = 0;
@@ -285,10 +294,35 @@ __global__ __launch_bounds__(kScanBlock) void k_cell_scan(int *__restrict__ coun
         const int c = count[k];
         start[k] = run;
         cursor[k] = run;
-        count[k] = 0;
         run += c;
+        atomicAdd(&bins[kOrderBins - 1 - min(c, kOrderBins - 1)], 1);
     }
     if (t == kScanBlock - 1) start[total] = wsum[kScanBlock / 64 - 1];
+    __syncthreads();
+    if (w == 0) {  // exclusive scan of the bins, four per lane
+        int v[4], sum = 0;
+        for (int q = 0; q < 4; ++q) {
+            v[q] = bins[4 * lane + q];
+            sum += v[q];
+        }
+        int y = sum;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int u = __shfl_up(y, d, 64);
+            if (lane >= d) y += u;
+        }
+        int e = y - sum;
+        for (int q = 0; q < 4; ++q) {
+            bins[4 * lane + q] = e;
+            e += v[q];
+        }
+    }
+    __syncthreads();
+    for (int k = a; k < b; ++k) {
+        const int c = count[k];
+        corder[atomicAdd(&bins[kOrderBins - 1 - min(c, kOrderBins - 1)], 1)] = k;
+        count[k] = 0;
+    }
     for (int k = t; k < 6 * nclusters; k += kScanBlock) box[k] = ord_encode((k % 6) < 3 ? INFINITY : -INFINITY);
 }
 
@@ -349,6 +383,7 @@ constexpr int kCellNbrCap = 512;  // listed candidates within rc per atom (an at
 
 template <int PREC, bool GEN, bool FORCE>
 __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *__restrict__ grid,
+                                                                const int *__restrict__ corder,
                                                                 const int *__restrict__ cell_cluster,
                                                                 const int *__restrict__ start,
                                                                 const double4 *__restrict__ rs,
@@ -366,7 +401,7 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
                   *const lw = lds_c + 3 * kCellStage;
     __shared__ int seg_lo[9], seg_len[9], seg_off[10];
     __shared__ int queue[kCellWaves][kCellQueue];
-    const int cell = blockIdx.x;
+    const int cell = corder[blockIdx.x];
     const CellGrid g = grid[cell_cluster[cell]];
     const int local = cell - g.base;
     if (local >= g.nx * g.ny * g.nz) return;  // uniform per workgroup
@@ -524,8 +559,9 @@ hipError_t launch_cell_sweep(CellList *cl, double *part, const double4 *xp, cons
     (void)hipGetLastError();
     const dim3 grid(cl->total_cap), block(64 * kCellWaves);
     const size_t lds = kCellStage * sizeof(double4);
-#define SCMD_CELL_ARGS \
-    cl->grid, cl->cell_cluster, cl->start, cl->rs, cl->sperm, cl->pslot, part, cl->tile_shift, cl->nbr, cl->nbr_n, xp, pc
+#define SCMD_CELL_ARGS                                                                                          \
+    cl->grid, cl->corder, cl->cell_cluster, cl->start, cl->rs, cl->sperm, cl->pslot, part, cl->tile_shift, cl->nbr, \
+        cl->nbr_n, xp, pc
     if (precision == SCMD_FP64) {
         if (pc.generic)
             hipLaunchKernelGGL((k_cell_sweep<SCMD_FP64, true, FORCE>), grid, block, lds, s, SCMD_CELL_ARGS);
@@ -557,7 +593,7 @@ void cell_list_destroy(CellList *cl) {
     if (!cl) return;
     void *ptrs[] = {cl->grid0, cl->grid,  cl->cell_cluster, cl->count,        cl->start, cl->cursor, cl->cell_of,
                     cl->perm,  cl->sperm, cl->box,          cl->chunks,       cl->pslot, cl->atom_cluster,
-                    cl->rs,    cl->nbr,   cl->nbr_n};
+                    cl->rs,    cl->nbr,   cl->nbr_n,        cl->corder};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete cl;
@@ -628,6 +664,7 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
     if ((e = dalloc(&cl->count, base)) != hipSuccess) return e;
     if ((e = dalloc(&cl->start, base + 1)) != hipSuccess) return e;
     if ((e = dalloc(&cl->cursor, base)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->corder, base)) != hipSuccess) return e;
     if ((e = dalloc(&cl->cell_of, natoms)) != hipSuccess) return e;
     if ((e = dalloc(&cl->perm, natoms)) != hipSuccess) return e;
     if ((e = dalloc(&cl->sperm, natoms)) != hipSuccess) return e;
@@ -670,8 +707,8 @@ hipError_t cell_list_build(CellList *cl, const double4 *rp, hipStream_t s) {
     if (na > 0)
         hipLaunchKernelGGL(k_cell_count, dim3((na + 255) / 256), dim3(256), 0, s, cl->grid0, cl->grid, cl->box, cl->rc,
                            cl->atom_cluster, rp, cl->cell_of, cl->count, na);
-    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(kScanBlock), 0, s, cl->count, cl->start, cl->cursor, tc, cl->box,
-                       cl->nclusters);
+    hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(kScanBlock), 0, s, cl->count, cl->start, cl->cursor, cl->corder, tc,
+                       cl->box, cl->nclusters);
     if (na > 0)
         hipLaunchKernelGGL(k_cell_scatter, dim3((na + 255) / 256), dim3(256), 0, s, cl->cell_of, cl->cursor, cl->perm,
                            na);
