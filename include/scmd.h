@@ -168,7 +168,9 @@ int scmd_set_potential(scmd_ctx *ctx, const scmd_sc_params *params);
 
 /* Time step dt_fs > 0 (the paper uses 1 fs), precision SCMD_FP64 or
  * SCMD_MIXED, neighbour SCMD_ALLPAIRS (needs rc == 0) or SCMD_CELLLIST
- * (needs rc > 0). */
+ * (needs rc > 0; the cell list keeps about 1 KiB of device memory per atom
+ * for the neighbours each atom's density sweep finds, plus O(cells) for the
+ * grid). */
 int scmd_set_integrator(scmd_ctx *ctx, double dt_fs, int precision, int neighbour);
 
 /* Thermostat of one cluster (cluster = -1: every cluster).  Berendsen: after
