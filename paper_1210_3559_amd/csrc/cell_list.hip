@@ -20,10 +20,11 @@
 //           per cell and wavefront);
 //   order   per cell: every atom's slot becomes its rank by atom index, so
 //           the cell-sorted order is deterministic; positions are gathered.
-// Sweeps: one workgroup per cell; the candidates of the 27 neighbouring cells
-// (9 contiguous x-rows of the sorted arrays) are staged in LDS, and each
-// wavefront takes the cell's atoms one at a time with its lanes across the
-// candidates.  Every atom's sum is complete after one sweep, so the tiles of
+// Sweeps: one workgroup per cell (fullest cells first); the candidates of
+// the 27 neighbouring cells (9 contiguous x-rows of the sorted arrays) are
+// staged in LDS, and each wavefront takes the cell's atoms one at a time
+// with its lanes across the candidates, testing them against rc before the
+// pair terms.  Every atom's sum is complete after one sweep, so the tiles of
 // the all-pairs plan are finished by the same reduce kernels with one slot
 // per tile.
 #include <algorithm>
@@ -366,16 +367,19 @@ __global__ __launch_bounds__(64) void k_cell_order(const int *__restrict__ start
 // ---------------------------------------------------------------------------
 // Sweeps
 // ---------------------------------------------------------------------------
-// One workgroup of kCellWaves wavefronts per cell.  The cell's 27-cell
-// neighbourhood is 9 x-rows, each contiguous in the sorted arrays; their
-// atoms (the candidates, concatenated row after row) are staged in LDS when
-// they fit.  Wavefront w takes the cell's atoms w, w + kCellWaves, ... one at
-// a time; for each, its lanes sweep the candidates (lane l takes l, l + 64,
-// ...) and a fixed-order DPP reduction adds the 64 lane sums, so every atom's sum
-// has one order whatever the launch (deterministic).  The atom itself sits
-// in the own row at one known candidate index (the self pair).
-// Neighbourhoods larger than the LDS buffer (only when cells coarsened after
-// an atom escaped) read the same candidates from global memory.
+// One workgroup of kCellWaves wavefronts per cell, the cells taken in the
+// scan's order (fullest first).  The cell's 27-cell neighbourhood is 9
+// x-rows, each contiguous in the sorted arrays; their atoms (the candidates,
+// concatenated row after row) are staged in LDS when they fit.  Wavefront w
+// takes the cell's atoms w, w + kCellWaves, ... one at a time; for each, its
+// lanes test the candidates against rc, the hits go through a queue to full
+// passes of the pair terms (the force sweep reads the hits the density sweep
+// stored), and a fixed-order DPP reduction adds the 64 lane sums.  The hits
+// and their order depend only on the positions, so every atom's sum has one
+// order whatever the launch (deterministic).  The atom itself sits in the own
+// row at one known candidate index (the self pair).  Neighbourhoods larger
+// than the LDS buffer (only when cells coarsened after an atom escaped) read
+// every candidate from global memory and mask the pairs beyond rc.
 constexpr int kCellWaves = 16;
 constexpr int kCellStage = 2048;  // staged candidates (64 KiB: two workgroups per CU)
 constexpr int kCellQueue = 128;   // in-range candidates queued per wavefront (< 64 left + 64 new)
