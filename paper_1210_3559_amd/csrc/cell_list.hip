@@ -296,7 +296,12 @@ __global__ __launch_bounds__(kScanBlock) void k_cell_scan(int *__restrict__ coun
         start[k] = run;
         cursor[k] = run;
         run += c;
-        atomicAdd(&bins[kOrderBins - 1 - min(c, kOrderBins - 1)], 1);
+        if (c == 0) {  // the empty cells (most of the capacity): one LDS atomic per wavefront
+            const unsigned long long zm = __ballot(1);
+            if (lane == __builtin_ctzll(zm)) atomicAdd(&bins[kOrderBins - 1], __popcll(zm));
+        } else {
+            atomicAdd(&bins[kOrderBins - 1 - min(c, kOrderBins - 1)], 1);
+        }
     }
     if (t == kScanBlock - 1) start[total] = wsum[kScanBlock / 64 - 1];
     __syncthreads();
@@ -321,7 +326,18 @@ __global__ __launch_bounds__(kScanBlock) void k_cell_scan(int *__restrict__ coun
     __syncthreads();
     for (int k = a; k < b; ++k) {
         const int c = count[k];
-        corder[atomicAdd(&bins[kOrderBins - 1 - min(c, kOrderBins - 1)], 1)] = k;
+        int pos;
+        if (c == 0) {
+            const unsigned long long zm = __ballot(1);
+            const int leader = __builtin_ctzll(zm);
+            int b0 = 0;
+            if (lane == leader) b0 = atomicAdd(&bins[kOrderBins - 1], __popcll(zm));
+            pos = __builtin_amdgcn_readlane(b0, leader) +
+                  __builtin_amdgcn_mbcnt_hi((unsigned)(zm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)zm, 0u));
+        } else {
+            pos = atomicAdd(&bins[kOrderBins - 1 - min(c, kOrderBins - 1)], 1);
+        }
+        corder[pos] = k;
         count[k] = 0;
     }
     for (int k = t; k < 6 * nclusters; k += kScanBlock) box[k] = ord_encode((k % 6) < 3 ? INFINITY : -INFINITY);
