@@ -294,6 +294,41 @@ int scmd_get_forces_device(scmd_ctx *ctx, double *dev_out);
 int scmd_rdf(scmd_ctx *ctx, int cluster, double r_select, double dr, int nbins, uint64_t *counts,
              int64_t *n_ref);
 
+/* Frames for the self-diffusion coefficient (Sec. 3, "Diffusion coefficient
+ * as a fingerprint of solidification phase transition").  scmd_set_frames
+ * gives cluster `cluster` a device store that keeps its last `capacity`
+ * frames (positions; 32 bytes per atom and frame), replacing and clearing any
+ * store it had; capacity = 0 removes the store.  SCMD_ENOMEM when the store
+ * cannot be allocated.  scmd_init_clusters removes every store. */
+int scmd_set_frames(scmd_ctx *ctx, int cluster, int capacity);
+
+/* Append the current positions of every cluster that has a frame store
+ * (enqueued on the context stream; does not wait).  Frames are numbered from
+ * 0 in the order recorded since the store was set. */
+int scmd_record_frame(scmd_ctx *ctx);
+
+/* Frames recorded into the cluster's store since it was set (SCMD_EINVAL if
+ * the cluster has no store). */
+int scmd_get_frame_count(scmd_ctx *ctx, int cluster, int64_t *recorded);
+
+/* Self-diffusion coefficient D = <dr^2> / (2 z dt), z = 3 (Sec. 3,
+ * Eq. (diffusion)), of the atoms of one cluster that lie closer than `radius`
+ * (A) to the centre of mass of frame `first`, from the frames [first, first +
+ * nframes) recorded frame_dt_ps apart (all still held by the store).  Every
+ * frame of the window is first moved onto frame `first` by the proper
+ * rotation and translation that minimise the summed squared displacement of
+ * all the cluster's atoms (the paper removes the cluster's overall motion
+ * this way); the window is cut into `segments` consecutive runs of
+ * floor(nframes / segments) >= 2 frames (trailing frames unused), dr is a
+ * central atom's displacement between the first and the last frame of a run
+ * and dt the time between them; D (A^2/ps; 1 A^2/ps = 1e-4 cm^2/s) is the
+ * mean over the central atoms and the runs, *n_central their number.
+ * Synchronises the context stream.  SCMD_EINVAL for a bad window, radius or
+ * dt, or when no atom is within radius (outputs then untouched).  An atom
+ * within rounding of the radius sphere may be classed either way. */
+int scmd_diffusion(scmd_ctx *ctx, int cluster, int64_t first, int nframes, double frame_dt_ps, double radius,
+                   int segments, double *D_A2_per_ps, int64_t *n_central);
+
 /* Checkpoint: scmd_get_state writes a self-describing blob (positions,
  * velocities, forces, thermostat factors and settings, step counts) into buf
  * of *bytes capacity; with buf NULL it only stores the needed size in *bytes.

@@ -241,6 +241,17 @@ hipError_t launch_sample(const ClusterState *st, int nclusters, double *ring, in
 hipError_t launch_rdf(const double4 *rp, int off, int n, double r_select, double dr, int nbins, int32_t *refs,
                       int *nref, unsigned long long *counts, hipStream_t s);
 
+// Frame store of the diffusion coefficient (analysis.hip): copy the atoms
+// [off, off + n) of rp to dst (n entries).
+hipError_t launch_store_frame(const double4 *rp, int off, int n, double4 *dst, hipStream_t s);
+// Diffusion coefficient from the window of frames [first, first + segments *
+// seg) of a ring of `cap` frames of n atoms: seg_d (segments entries) receives
+// each segment's coefficient, *ncentral the central atoms, *d_out the mean
+// (A^2/ps).
+hipError_t launch_diffusion(const double4 *frames, int n, int cap, int64_t first, int seg, int segments,
+                            double radius, double dt_ps, double *seg_d, int *ncentral, double *d_out,
+                            hipStream_t s);
+
 // Number of doubles per tile in tile_sums: [0] sum e_emb, [1] sum e_pair,
 // [2] sum v^2.
 constexpr int kTileSums = 4;

@@ -92,6 +92,16 @@ struct scmd_ctx {
     DevBuf<int32_t> rdf_refs;
     DevBuf<int> rdf_nref;
     DevBuf<unsigned long long> rdf_counts;
+    // frame stores of the diffusion coefficient (one per cluster that has one)
+    struct FrameStore {
+        int cluster = 0;
+        int cap = 0;
+        int64_t recorded = 0;
+        DevBuf<double4> buf;
+    };
+    std::vector<FrameStore> frames;
+    DevBuf<double> diff_seg;  // per-segment coefficients, then the mean
+    DevBuf<int> diff_ncentral;
     int *h_flag = nullptr;  // pinned
 
     // all-pairs plan
@@ -911,6 +921,10 @@ void release_device(scmd_ctx *c) {
     c->d_stiles.release();
     c->d_ipart.release();
     c->d_jpart.release();
+    for (auto &fs : c->frames) fs.buf.release();
+    c->frames.clear();
+    c->diff_seg.release();
+    c->diff_ncentral.release();
     if (c->cells) {
         cell_list_destroy(c->cells);
         c->cells = nullptr;
@@ -1478,6 +1492,99 @@ int scmd_rdf(scmd_ctx *ctx, int cluster, double r_select, double dr, int nbins, 
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
         for (int b = 0; b < nbins; ++b) counts[b] += h[b];
         *n_ref += nr;
+        return SCMD_OK;
+    })
+}
+
+int scmd_set_frames(scmd_ctx *ctx, int cluster, int capacity) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
+    if (cluster < 0 || cluster >= ctx->nclusters) return fail(ctx, SCMD_EINVAL, "cluster index out of range");
+    if (capacity < 0) return fail(ctx, SCMD_EINVAL, "capacity must be >= 0");
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        for (size_t k = 0; k < ctx->frames.size(); ++k) {
+            if (ctx->frames[k].cluster == cluster) {
+                ctx->frames[k].buf.release();
+                ctx->frames.erase(ctx->frames.begin() + (long)k);
+                break;
+            }
+        }
+        if (capacity == 0) return SCMD_OK;
+        const size_t n = (size_t)(ctx->offsets[cluster + 1] - ctx->offsets[cluster]);
+        scmd_ctx::FrameStore fs;
+        fs.cluster = cluster;
+        fs.cap = capacity;
+        if (fs.buf.ensure(std::max<size_t>((size_t)capacity * n, 1)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, SCMD_ENOMEM, "frame store allocation failed");
+        }
+        ctx->frames.push_back(fs);
+        return SCMD_OK;
+    })
+}
+
+int scmd_record_frame(scmd_ctx *ctx) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        for (auto &fs : ctx->frames) {
+            const int off = (int)ctx->offsets[fs.cluster];
+            const int n = (int)(ctx->offsets[fs.cluster + 1] - ctx->offsets[fs.cluster]);
+            const size_t slot = (size_t)(fs.recorded % fs.cap);
+            HIP_TRY(ctx, launch_store_frame(ctx->rp.p, off, n, fs.buf.p + slot * (size_t)n, ctx->stream));
+            ++fs.recorded;
+        }
+        return SCMD_OK;
+    })
+}
+
+int scmd_get_frame_count(scmd_ctx *ctx, int cluster, int64_t *recorded) {
+    if (!ctx || !recorded) return SCMD_EINVAL;
+    for (const auto &fs : ctx->frames) {
+        if (fs.cluster == cluster) {
+            *recorded = fs.recorded;
+            return SCMD_OK;
+        }
+    }
+    return fail(ctx, SCMD_EINVAL, "the cluster has no frame store");
+}
+
+int scmd_diffusion(scmd_ctx *ctx, int cluster, int64_t first, int nframes, double frame_dt_ps, double radius,
+                   int segments, double *D_A2_per_ps, int64_t *n_central) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!D_A2_per_ps || !n_central) return fail(ctx, SCMD_EINVAL, "D_A2_per_ps or n_central is NULL");
+    const scmd_ctx::FrameStore *fs = nullptr;
+    for (const auto &x : ctx->frames)
+        if (x.cluster == cluster) fs = &x;
+    if (!fs) return fail(ctx, SCMD_EINVAL, "the cluster has no frame store");
+    if (segments < 1 || nframes < 0 || nframes / segments < 2)
+        return fail(ctx, SCMD_EINVAL, "need segments >= 1 and at least two frames per segment");
+    if (!(frame_dt_ps > 0.0) || !std::isfinite(frame_dt_ps)) return fail(ctx, SCMD_EINVAL, "need frame_dt_ps > 0");
+    if (!(radius > 0.0) || !std::isfinite(radius)) return fail(ctx, SCMD_EINVAL, "need a finite radius > 0");
+    if (first < 0 || first + nframes > fs->recorded || first < fs->recorded - fs->cap)
+        return fail(ctx, SCMD_EINVAL, "frames outside those the store holds");
+    const int n = (int)(ctx->offsets[cluster + 1] - ctx->offsets[cluster]);
+    if (n < 1) return fail(ctx, SCMD_EINVAL, "empty cluster");
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        HIP_TRY(ctx, ctx->diff_seg.ensure((size_t)segments + 1));
+        HIP_TRY(ctx, ctx->diff_ncentral.ensure(1));
+        const int seg = nframes / segments;
+        HIP_TRY(ctx, launch_diffusion(fs->buf.p, n, fs->cap, first, seg, segments, radius, frame_dt_ps,
+                                      ctx->diff_seg.p, ctx->diff_ncentral.p, ctx->diff_seg.p + segments,
+                                      ctx->stream));
+        double d = 0.0;
+        int nc = 0;
+        HIP_TRY(ctx, hipMemcpyAsync(&d, ctx->diff_seg.p + segments, sizeof(double), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(&nc, ctx->diff_ncentral.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        if (nc == 0) return fail(ctx, SCMD_EINVAL, "no atom within radius of the centre of mass");
+        *D_A2_per_ps = d;
+        *n_central = nc;
         return SCMD_OK;
     })
 }

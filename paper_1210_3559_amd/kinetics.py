@@ -23,9 +23,22 @@ import time
 
 import numpy as np
 
-from . import diffusion, inputs, scmd
+from . import inputs, scmd
 
 K_B = 8.617333262145179e-05  # eV/K
+A2_PER_PS_TO_CM2_PER_S = 1e-4  # 1 A^2/ps = 1e-16 cm^2 / 1e-12 s
+
+
+def rdf_g(counts, n_ref: int, dr: float, rho_bar: float = 4.0 / 3.52 ** 3):
+    """g(r) = rho(r) / rho_bar (Sec. 3, Eq. (Rdist)) at the bin centres from a
+    pair-distance histogram: counts / (n_ref rho_bar V_shell), V_shell the
+    volume of the bin's spherical shell; rho_bar defaults to the number
+    density of fcc nickel, 4 / a^3."""
+    c = np.asarray(counts, dtype=np.float64)
+    b = np.arange(len(c), dtype=np.float64)
+    shell = 4.0 * np.pi / 3.0 * ((b + 1.0) ** 3 - b ** 3) * dr ** 3
+    r = (b + 0.5) * dr
+    return r, c / (max(int(n_ref), 1) * rho_bar * shell)
 
 
 def running_mean(x, w: int) -> np.ndarray:
@@ -96,24 +109,25 @@ def fit_rate3(T, kappa_per_ps, T0=None, p0=(1.2, 3.0e4, 1030.0)):
     return tuple(float(v) for v in p)
 
 
-def structure_series(frames, frame_ps: float, rdf_counts, rdf_nref, window_ps: float = 1000.0,
-                     stride_ps: float = 500.0, radius: float = 10.0, segments: int = 10, dr: float = 0.4):
+def structure_series(sim, cluster: int, nframes: int, frame_ps: float, rdf_counts, rdf_nref,
+                     window_ps: float = 1000.0, stride_ps: float = 500.0, radius: float = 10.0, segments: int = 10,
+                     dr: float = 0.4):
     """D(t) and g(r) of one trajectory as the paper computes them: at window
-    centres every stride_ps, D from the frames within +-window/2 (10
-    segments, central atoms within `radius`), g(r) of the central atoms
-    (per-frame histograms summed over the window)."""
-    fr = np.asarray(frames)
+    centres every stride_ps, D from the window's frames held in the cluster's
+    device frame store (10 segments, central atoms within `radius`; computed
+    by the library), g(r) of the central atoms (per-frame histograms summed
+    over the window)."""
     nwin = max(1, int(round(window_ps / frame_ps)))
     out = []
     centre = window_ps / 2.0
-    while (centre + window_ps / 2.0) / frame_ps <= len(fr) + 1e-9:
+    while (centre + window_ps / 2.0) / frame_ps <= nframes + 1e-9:
         a = int(round((centre - window_ps / 2.0) / frame_ps))
-        b = min(len(fr), a + nwin)
-        d, nc = diffusion.diffusion_coefficient(fr[a:b], frame_ps, radius, segments)
+        b = min(nframes, a + nwin)
+        d, nc = sim.diffusion(cluster, a, b - a, frame_ps, radius, segments)
         cnt = np.sum(rdf_counts[a:b], axis=0)
         nref = int(np.sum(rdf_nref[a:b]))
-        r, g = scmd.rdf_g(cnt, nref, dr)
-        out.append({"t_ps": centre, "D_cm2_per_s": d * diffusion.A2_PER_PS_TO_CM2_PER_S, "central_atoms": nc,
+        r, g = rdf_g(cnt, nref, dr)
+        out.append({"t_ps": centre, "D_cm2_per_s": d * A2_PER_PS_TO_CM2_PER_S, "central_atoms": nc,
                     "rdf_r": [float(x) for x in r], "rdf_g": [float(x) for x in g], "rdf_refs": nref})
         centre += stride_ps
     return out
@@ -142,7 +156,9 @@ def run(T: float, replicas: int = 15, max_ps: float = 4000.0, T_melt: float = 14
             sim.set_thermostat(k, dict(w.thermostat[k], T_start=T, T_end=T, ramp_steps=0))
         done, found = 0, [None] * replicas
         fstep = max(every, int(round(frame_ps * 1000.0 / dt)) // every * every) if track > 0 else chunk
-        frames = [[] for _ in range(track)]
+        for k in range(track):
+            sim.set_frames(k, max_steps // fstep + 1)
+        nframes = 0
         hists = [[] for _ in range(track)]
         nrefs = [[] for _ in range(track)]
         while done < max_steps:
@@ -153,9 +169,9 @@ def run(T: float, replicas: int = 15, max_ps: float = 4000.0, T_melt: float = 14
                 sim.step(f)
                 left -= f
                 if track > 0 and f == fstep:
-                    pos = sim.positions()
+                    sim.record_frame()
+                    nframes += 1
                     for k in range(track):
-                        frames[k].append(pos[w.offsets[k]:w.offsets[k + 1]].copy())
                         h, nr = sim.rdf(k, rdf_dr, rdf_bins, rdf_select)
                         hists[k].append(h)
                         nrefs[k].append(nr)
@@ -176,6 +192,8 @@ def run(T: float, replicas: int = 15, max_ps: float = 4000.0, T_melt: float = 14
             s, _ = sim.samples(k, cap)
             iso = s[s[:, 0] > melt_steps]
             traces.append(((iso[:, 0] - melt_steps) * dt * 1e-3, (iso[:, 1] + iso[:, 2]) / n, iso[:, 3]))
+        series = [structure_series(sim, k, nframes, frame_ps, hists[k], nrefs[k], dr=rdf_dr) for k in range(track)
+                  if nframes * frame_ps >= 1000.0]
     wall = time.perf_counter() - t0
     run_ps = done * dt * 1e-3
     life = [x for x in found if x is not None]
@@ -188,8 +206,6 @@ def run(T: float, replicas: int = 15, max_ps: float = 4000.0, T_melt: float = 14
             liq = np.median(ek[(tk >= 10.0) & (tk <= max(20.0, x - 5.0))])
             sol = np.median(ek[tk >= tk[-1] - 30.0])
             lat.append(float(liq - sol) * n)
-    series = [structure_series(frames[k], frame_ps, hists[k], nrefs[k], dr=rdf_dr) for k in range(track)
-              if len(frames[k]) * frame_ps >= 1000.0]
     return {
         "T_K": T, "replicas": replicas, "atoms_per_cluster": n, "gamma_per_ps": gamma, "dt_fs": dt,
         "tracked": series,

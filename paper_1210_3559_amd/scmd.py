@@ -46,7 +46,8 @@ EXPORTS = (
     "scmd_step", "scmd_step_async", "scmd_synchronize", "scmd_get_step", "scmd_get_energy",
     "scmd_get_temperature", "scmd_get_positions", "scmd_get_velocities", "scmd_get_forces", "scmd_get_density",
     "scmd_get_forces_device", "scmd_get_state", "scmd_set_state", "scmd_set_profiling", "scmd_get_kernel_time",
-    "scmd_set_sampling", "scmd_get_samples", "scmd_rdf", "scmd_last_error",
+    "scmd_set_sampling", "scmd_get_samples", "scmd_rdf", "scmd_set_frames", "scmd_record_frame",
+    "scmd_get_frame_count", "scmd_diffusion", "scmd_last_error",
 )
 
 
@@ -110,6 +111,10 @@ def load(path: str = LIB_PATH):
         "scmd_get_density": (i32, [vp, dp]),
         "scmd_get_forces_device": (i32, [vp, vp]),
         "scmd_rdf": (i32, [vp, i32, dbl, dbl, i32, vp, ctypes.POINTER(i64)]),
+        "scmd_set_frames": (i32, [vp, i32, i32]),
+        "scmd_record_frame": (i32, [vp]),
+        "scmd_get_frame_count": (i32, [vp, i32, ctypes.POINTER(i64)]),
+        "scmd_diffusion": (i32, [vp, i32, i64, i32, dbl, dbl, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
         "scmd_get_state": (i32, [vp, vp, ctypes.POINTER(ctypes.c_size_t)]),
         "scmd_set_state": (i32, [vp, vp, ctypes.c_size_t]),
         "scmd_set_profiling": (i32, [vp, i32]),
@@ -300,14 +305,28 @@ def scmd_rdf(ctx, cluster: int, dr: float, nbins: int, r_select: float = 0.0, co
     return out, int(nr.value)
 
 
-def rdf_g(counts, n_ref: int, dr: float, rho_bar: float = 4.0 / 3.52 ** 3):
-    """g(r) at the bin centres from a histogram: counts / (n_ref rho_bar
-    V_shell); rho_bar defaults to the fcc nickel number density 4/a^3."""
-    c = np.asarray(counts, dtype=np.float64)
-    b = np.arange(len(c), dtype=np.float64)
-    shell = 4.0 * np.pi / 3.0 * ((b + 1.0) ** 3 - b ** 3) * dr ** 3
-    r = (b + 0.5) * dr
-    return r, c / (max(int(n_ref), 1) * rho_bar * shell)
+def scmd_set_frames(ctx, cluster: int, capacity: int) -> None:
+    _check(ctx, load().scmd_set_frames(ctx, int(cluster), int(capacity)))
+
+
+def scmd_record_frame(ctx) -> None:
+    _check(ctx, load().scmd_record_frame(ctx))
+
+
+def scmd_get_frame_count(ctx, cluster: int) -> int:
+    n = ctypes.c_int64()
+    _check(ctx, load().scmd_get_frame_count(ctx, int(cluster), ctypes.byref(n)))
+    return n.value
+
+
+def scmd_diffusion(ctx, cluster: int, first: int, nframes: int, frame_dt_ps: float, radius: float = 10.0,
+                   segments: int = 10):
+    """(D in A^2/ps, number of central atoms) from stored frames."""
+    d = ctypes.c_double()
+    nc = ctypes.c_int64()
+    _check(ctx, load().scmd_diffusion(ctx, int(cluster), int(first), int(nframes), float(frame_dt_ps),
+                                      float(radius), int(segments), ctypes.byref(d), ctypes.byref(nc)))
+    return d.value, nc.value
 
 
 def scmd_get_state(ctx) -> bytes:
@@ -441,3 +460,16 @@ class Simulation:
 
     def rdf(self, cluster: int, dr: float, nbins: int, r_select: float = 0.0, counts=None, n_ref: int = 0):
         return scmd_rdf(self.ctx, cluster, dr, nbins, r_select, counts, n_ref)
+
+    def set_frames(self, cluster: int, capacity: int):
+        scmd_set_frames(self.ctx, cluster, capacity)
+
+    def record_frame(self):
+        scmd_record_frame(self.ctx)
+
+    def frame_count(self, cluster: int) -> int:
+        return scmd_get_frame_count(self.ctx, cluster)
+
+    def diffusion(self, cluster: int, first: int, nframes: int, frame_dt_ps: float, radius: float = 10.0,
+                  segments: int = 10):
+        return scmd_diffusion(self.ctx, cluster, first, nframes, frame_dt_ps, radius, segments)

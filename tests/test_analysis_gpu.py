@@ -86,3 +86,90 @@ def test_rdf_argument_errors():
             assert e.value.status == scmd.SCMD_EINVAL
         with pytest.raises(scmd.ScmdError):
             sim.rdf(0, 0.1, 10, r_select=np.nan)
+
+
+# ---------------------------------------------------------------------------
+# Diffusion coefficient (Sec. 3, Eq. (diffusion)) from the device frame store
+# against the oracle's SVD-based superposition on the same frames.  The two
+# sides find the optimal rotation by different methods (quaternion
+# eigenvector on the device, singular value decomposition in the oracle) and
+# sum in different orders, so D agrees to rounding (1e-9 relative); the
+# number of central atoms is exact once no atom sits within 1e-9 A of the
+# radius sphere.
+# ---------------------------------------------------------------------------
+def _central_tie_free(ref, radius, margin=1e-9):
+    d = np.sqrt(((ref - ref.mean(axis=0)) ** 2).sum(axis=1))
+    return np.all(np.abs(d - radius) > margin)
+
+
+def _trajectory_frames(sim, k, off, nframes, every):
+    frames = []
+    for _ in range(nframes):
+        sim.step(every)
+        sim.record_frame()
+        frames.append(sim.positions()[off[k]:off[k + 1]].copy())
+    return np.stack(frames)
+
+
+@pytest.mark.parametrize("first,nframes,segments,radius", [(0, 60, 10, 8.0), (7, 45, 4, 6.5), (0, 60, 1, 1e6),
+                                                            (30, 30, 15, 9.0)])
+def test_diffusion_matches_oracle_on_a_hot_cluster(first, nframes, segments, radius):
+    from oracle import diffusion as odiff
+    rng = np.random.default_rng(601)
+    pos = inputs.jitter(inputs.fcc_exact(600), 0.05, rng)
+    vel = inputs.maxwell_boltzmann(pos, 2200.0, rng)
+    print(f"[diffusion] Ni600 at 2200 K, window first={first} n={nframes} segments={segments}", flush=True)
+    with scmd.Simulation(np.array([0, 600]), pos, vel, dt=2.0) as sim:
+        sim.set_frames(0, 64)
+        frames = _trajectory_frames(sim, 0, [0, 600], 60, 10)
+        assert sim.frame_count(0) == 60
+        win = frames[first:first + nframes]
+        assert _central_tie_free(win[0], radius)
+        d, nc = sim.diffusion(0, first, nframes, 0.02, radius, segments)
+    d_ref, nc_ref = odiff.diffusion(win, 0.02, radius=radius, segments=segments)
+    assert nc == nc_ref
+    assert d > 0.0
+    assert d == pytest.approx(d_ref, rel=1e-9)
+
+
+def test_diffusion_of_a_batch_cluster_with_a_wrapped_store():
+    from oracle import diffusion as odiff
+    sizes = [147, 1000, 0, 320]
+    rng = np.random.default_rng(602)
+    parts = [inputs.jitter(inputs.fcc_exact(n), 0.05, rng) for n in sizes]
+    vels = [inputs.maxwell_boltzmann(p, 1900.0, rng) if len(p) else np.zeros((0, 3)) for p in parts]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    print("[diffusion] batch, stores on clusters 1 and 3, 50 frames in rings of 24 and 50", flush=True)
+    with scmd.Simulation(off, np.concatenate(parts), np.concatenate(vels), dt=1.0) as sim:
+        sim.set_frames(1, 24)
+        sim.set_frames(3, 50)
+        f1, f3 = [], []
+        for _ in range(50):
+            sim.step(8)
+            sim.record_frame()
+            p = sim.positions()
+            f1.append(p[off[1]:off[2]].copy())
+            f3.append(p[off[3]:off[4]].copy())
+        assert sim.frame_count(1) == 50 and sim.frame_count(3) == 50
+        # only the last 24 frames of cluster 1 are still held
+        with pytest.raises(scmd.ScmdError) as e:
+            sim.diffusion(1, 25, 24, 0.008, 7.0, 4)
+        assert e.value.status == scmd.SCMD_EINVAL
+        got1 = sim.diffusion(1, 26, 24, 0.008, 7.0, 4)
+        got3 = sim.diffusion(3, 0, 50, 0.008, 5.0, 5)
+        for args in [(0, 0, 10, 0.01, 5.0, 2), (3, 0, 51, 0.01, 5.0, 5), (3, 0, 9, 0.01, 5.0, 5),
+                     (3, 0, 50, 0.0, 5.0, 5), (3, 0, 50, 0.01, -1.0, 5), (3, 0, 50, 0.01, 5.0, 0),
+                     (3, -1, 20, 0.01, 5.0, 5), (3, 0, 50, 0.01, 1e-3, 5)]:
+            with pytest.raises(scmd.ScmdError) as e:
+                sim.diffusion(*args)
+            assert e.value.status == scmd.SCMD_EINVAL
+        sim.set_frames(3, 0)
+        with pytest.raises(scmd.ScmdError):
+            sim.frame_count(3)
+    w1, w3 = np.stack(f1[26:50]), np.stack(f3)
+    assert _central_tie_free(w1[0], 7.0) and _central_tie_free(w3[0], 5.0)
+    ref1 = odiff.diffusion(w1, 0.008, radius=7.0, segments=4)
+    ref3 = odiff.diffusion(w3, 0.008, radius=5.0, segments=5)
+    assert got1[1] == ref1[1] and got3[1] == ref3[1]
+    assert got1[0] == pytest.approx(ref1[0], rel=1e-9)
+    assert got3[0] == pytest.approx(ref3[0], rel=1e-9)

@@ -81,7 +81,20 @@ def test_structure_series_windows():
     rng = np.random.default_rng(0)
     frames = np.cumsum(rng.normal(0, 0.2, (300, 400, 3)), axis=0) + rng.uniform(-8, 8, (400, 3))
     hist = [np.arange(40, dtype=np.uint64)] * 300
-    out = kinetics.structure_series(frames, 10.0, hist, [3] * 300, radius=1e9)
+
+    class FrameStore:
+        # stands in for the library's frame store: the window logic is under
+        # test here, the coefficient itself comes from the oracle
+        calls = []
+
+        def diffusion(self, cluster, first, nframes, frame_dt_ps, radius, segments):
+            from oracle import diffusion as odiff
+            self.calls.append((cluster, first, nframes))
+            return odiff.diffusion(frames[first:first + nframes], frame_dt_ps, radius, segments)
+
+    store = FrameStore()
+    out = kinetics.structure_series(store, 0, 300, 10.0, hist, [3] * 300, radius=1e9)
+    assert store.calls == [(0, 0, 100), (0, 50, 100), (0, 100, 100), (0, 150, 100), (0, 200, 100)]
     # 3 ns of frames: 1 ns windows centred every 0.5 ns
     assert [o["t_ps"] for o in out] == [500.0, 1000.0, 1500.0, 2000.0, 2500.0]
     for o in out:
