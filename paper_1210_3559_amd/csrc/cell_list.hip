@@ -633,8 +633,9 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
     hipError_t e;
     if (natoms > 0 && (e = hipMemcpy(r.data(), rp_dev, natoms * sizeof(double4), hipMemcpyDeviceToHost)) != hipSuccess)
         return e;
-    // cell capacity per cluster: twice the cells of the initial box per
-    // dimension plus a margin
+    // cell capacity per cluster: the cells of the initial box per dimension
+    // plus four (room for the cluster to expand by about two cells on each
+    // side before the grid coarsens), at most 1024
     std::vector<CellGrid> grids(nclusters);
     std::vector<int> cell_cluster;
     int base = 0;

@@ -148,6 +148,8 @@ def test_full_size_48k_sampled_against_oracle():
     assert np.all(per <= 1e-10 * np.maximum(np.linalg.norm(f_ref, axis=1), frms))
     # exact-arithmetic invariants at full size
     assert np.linalg.norm(f.sum(axis=0)) <= 1e-10 * np.abs(f).sum()
+    e_ref = oracle.energy(pos, nthreads=NT)
+    assert ens[0][0] == pytest.approx(e_ref, rel=1e-10)
 
 
 def test_full_size_15k_mixed_error_budget():
@@ -160,6 +162,52 @@ def test_full_size_15k_mixed_error_budget():
     frms = np.sqrt(np.mean(np.sum(f ** 2, axis=1)))
     per = np.linalg.norm(f[idx] - f_ref, axis=1)
     assert np.all(per <= 1e-5 * np.maximum(np.linalg.norm(f_ref, axis=1), frms))
+    assert ens[0][0] == pytest.approx(oracle.energy(w.pos, nthreads=NT), rel=1e-5)
+
+
+def _mixed_errors(sim, n, idx):
+    """Force (norm-wise over the sample, worst per atom) and energy errors of
+    the mixed form against the FP64 oracle at the GPU's current positions."""
+    pos, f, e = sim.positions(), sim.forces(), sim.energy()[0]
+    f_ref, _ = oracle.forces_subset(pos, idx, nthreads=NT)
+    frms = np.sqrt(np.mean(np.sum(f ** 2, axis=1)))
+    per = np.linalg.norm(f[idx] - f_ref, axis=1) / np.maximum(np.linalg.norm(f_ref, axis=1), frms)
+    e_ref = oracle.energy(pos, nthreads=NT)
+    return (np.linalg.norm(f[idx] - f_ref) / np.linalg.norm(f_ref), float(per.max()), abs(e - e_ref) / abs(e_ref))
+
+
+def test_c4_mixed_error_along_the_run():
+    # the precision form at 15,000 atoms, 1500 K NVE: force and energy error
+    # against the FP64 oracle (evaluated at the GPU's positions) at steps 0,
+    # 1000 and 10000
+    w = inputs.c4_mixed()
+    idx = np.random.default_rng(4).choice(w.n_atoms, 64, replace=False)
+    with scmd.Simulation.from_workload(w, precision="mixed") as sim:
+        sim.compute()
+        errs = {0: _mixed_errors(sim, w.n_atoms, idx)}
+        for k, n in ((1000, 1000), (10000, 9000)):
+            sim.step(n)
+            errs[k] = _mixed_errors(sim, w.n_atoms, idx)
+    for k, (fn, fw, ee) in errs.items():
+        print(f"[mixed] step {k}: force rel-norm {fn:.2e}, worst atom {fw:.2e}, energy {ee:.2e}", flush=True)
+        assert fn <= 1e-5 and fw <= 1e-5 and ee <= 1e-5
+
+
+def test_mixed_nve_drift_below_bound():
+    # 0.5 ns of Ni147 NVE in the mixed form: drift slope of E_tot/N below
+    # 1e-4 eV/atom/ns
+    w = inputs.c1_icosahedron()
+    print("[traj] Ni147 NVE 510k steps, mixed", flush=True)
+    with scmd.Simulation.from_workload(w, precision="mixed") as sim:
+        sim.step(10000)
+        t, e = [], []
+        for k in range(100):
+            sim.step(5000)
+            t.append(scmd.scmd_get_step(sim.ctx) * 1e-6)
+            e.append(sim.energy()[2] / 147)
+    slope = np.polyfit(np.array(t), np.array(e), 1)[0]
+    print(f"[traj] mixed drift slope {slope:.3e} eV/atom/ns", flush=True)
+    assert abs(slope) < 1e-4
 
 
 # --------------------------------------------------------------------------
@@ -360,6 +408,14 @@ def test_cell_list_crowded_neighbourhoods(precision):
     check_single(_cluster(600, seed=600, amp=0.2), precision=precision, params=dict(rc=16.0))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cell_list_unstaged_neighbourhoods(precision):
+    # rc = 16 A over the 2243-atom cut (36 A across): the 27-cell
+    # neighbourhoods of the central cells hold more candidates than the LDS
+    # stage (2048), so their sweeps read the candidates from global memory
+    check_single(inputs.c2_cooling().pos, precision=precision, params=dict(rc=16.0))
+
+
 def test_cell_list_batch_with_escaped_atom():
     # an atom that leaves its cluster after the grid was planned stretches the
     # box beyond the cell capacity: cells coarsen, results stay exact
@@ -411,6 +467,7 @@ def test_cell_list_full_size_48k_sampled():
     frms = np.sqrt(np.mean(np.sum(f ** 2, axis=1)))
     per = np.linalg.norm(f[idx] - f_ref, axis=1)
     assert np.all(per <= 1e-10 * np.maximum(np.linalg.norm(f_ref, axis=1), frms))
+    assert ens[0][0] == pytest.approx(oracle.energy(w.pos, params=dict(rc=RC), nthreads=NT), rel=1e-10)
 
 
 def test_cell_list_is_deterministic():
