@@ -5,24 +5,30 @@
 
 One step is a whole velocity-Verlet step of every cluster of the workload
 (drift, density sweep, density reduce, force sweep, force reduce + kick,
-thermostat), replayed from captured HIP graphs, with the inputs resident in
-HBM before the timed region starts.  The default workload is a 2243-atom
-spherical fcc Ni cut (R = 18 A), +-0.05 A jitter, Maxwell-Boltzmann start at
-2000 K, Berendsen cooling 2000 -> 800 K over 200k steps of 2 fs, all pairs,
-FP64.  Prints one JSON line:
+thermostat) with the inputs resident in HBM before the timed region starts.
+The K timed steps are one library call, replayed from captured HIP graphs
+(32-step graphs plus one graph of the remainder), exactly as a user's
+scmd_step runs them, with profiling off.  The default workload is the largest single-GPU
+all-pairs configuration: a 48,077-atom spherical fcc Ni cut (R = 50 A),
++-0.05 A jitter, Maxwell-Boltzmann start at 1900 K, Berendsen at 1900 K,
+dt = 1 fs, all pairs, FP64.  Prints one JSON line:
 
   value        whole-job atom-steps/s over exactly K timed steps
-  roofline     the force sweep (dominant kernel; on the cell list the longer
-               of the two sweeps): algorithmic FLOP per launch
-               (30 FLOP per unordered pair: a step without the pair-energy
-               term, like all but the last step of each 32-step graph) / its
-               device time per launch,
-               measured with HIP events inside the timed region, against the
-               FP64 vector peak of MI355X (78.6 TFLOP/s)
+  roofline     the dominant kernel (the force sweep; on the cell list the
+               longer of the two sweeps): algorithmic FLOP per launch (30
+               FLOP per unordered pair for a step without the pair-energy
+               term, which is every step but the last of a run, and the
+               sampled one) / its device time per launch, from HIP events
+               recorded inside the replayed graphs on the context stream
+               (one sampled step per replay) during a second timed call of
+               K steps, against the FP64 vector peak of MI355X (78.6
+               TFLOP/s)
   cpu_baseline the FP64 oracle on the host cores on a bounded sample of the
                same workload
   forms        the other forms measured briefly (mixed precision, batched,
-               large all-pairs, cell list) with their own rooflines
+               cell list, Langevin bath) with their own rooflines; mixed
+               forms also report their force and energy error against the
+               FP64 oracle at their final positions
 """
 from __future__ import annotations
 
@@ -39,13 +45,19 @@ if ROOT not in sys.path:
 import numpy as np  # noqa: E402
 
 METRIC = "atom-steps/s and pair-interactions/s, Ni SC MD at 1 GPU: FP64 vs mixed vs batched"
-PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector (256 CU x 2.4 GHz x 128 FLOP/clk/CU)
+# MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 FLOP/clk/CU).  The mixed
+# form's single-precision pair terms run as unpacked FP32 instructions (this
+# build disables packed FP32), whose issue rate is the FP64 vector rate, so
+# the same peak bounds both forms; the 157.3 TFLOP/s FP32 figure needs packed
+# two-wide instructions.
+PEAK_FP64_TFLOPS = 78.6
 FLOP_DENSITY_PER_PAIR = 13.0  # algorithmic FLOP per unordered pair, density sweep
 # algorithmic FLOP per unordered pair of the timed force sweep: 31 with the
 # pair-energy term, 30 without it; the library accumulates the pair energy
-# only on the last step of each run (32-step graph replays, sampled steps),
-# and the sampled launch is a step without it
+# only on the last step of each run, and the sampled launch is a step without it
 FLOP_FORCE_PER_PAIR = 30.0
+MIN_KERNEL_SAMPLES = 8
+ORACLE_FLAGS = "gcc -O2 -std=c11 -fopenmp -ffp-contract=off -fno-fast-math (no host-specific ISA)"
 
 
 def measured_traffic(workload: str):
@@ -80,30 +92,50 @@ def _workload(name: str):
         raise SystemExit(str(exc))
 
 
-def time_gpu(w, steps: int, warmup: int, tuning=None):
-    """Warm up, then time exactly `steps` steps; returns a result dict."""
+def _kernel_times(sim, scmd):
+    f_ms, f_n = scmd.scmd_get_kernel_time(sim.ctx, scmd.SCMD_KERNEL_FORCE)
+    d_ms, d_n = scmd.scmd_get_kernel_time(sim.ctx, scmd.SCMD_KERNEL_DENSITY)
+    return f_ms, f_n, d_ms, d_n
+
+
+def time_gpu(w, steps: int, warmup: int, tuning=None, keep_state: bool = False):
+    """Warm up, then time exactly `steps` steps in one library call; returns a
+    result dict (and the final positions, forces and per-cluster potential
+    energies under "state" when keep_state)."""
     import torch
 
     from paper_1210_3559_amd import scmd
     sim = scmd.Simulation.from_workload(w, tuning=tuning)
     try:
+        # warm-up; a run of steps % 32 steps captures the graph of the
+        # timed call's remainder, so the timed call only replays graphs
         sim.step(warmup)
-        scmd.scmd_set_profiling(sim.ctx, True)
-        # the timed steps go in chunks so that the sampled kernel times (one
-        # sample per graph replay, kept per call) cover the whole region
-        # whole 32-step graphs per chunk where possible (the remainder of a
-        # chunk runs eagerly), the rest of the steps in the last chunk
-        chunks = max(1, min(25, steps // 256))
-        per = (steps // chunks) // 32 * 32 or steps // chunks
-        sizes = [per] * (chunks - 1) + [steps - per * (chunks - 1)]
+        sim.step(steps % 32)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for n in sizes:
-            sim.step(n)
+        sim.step(steps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        f_ms, f_n = scmd.scmd_get_kernel_time(sim.ctx, scmd.SCMD_KERNEL_FORCE)
-        d_ms, d_n = scmd.scmd_get_kernel_time(sim.ctx, scmd.SCMD_KERNEL_DENSITY)
+        # kernel times: the same call again with profiling events recorded
+        # inside the replayed graphs (one sampled step per replay), timed on
+        # its own so that the events' cost shows
+        scmd.scmd_set_profiling(sim.ctx, True)
+        sim.step(steps % 32)
+        sim.step(32)
+        scmd.scmd_set_profiling(sim.ctx, True)  # resets the averages, keeps the graphs
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        dt_prof = time.perf_counter() - t0
+        f_ms, f_n, d_ms, d_n = _kernel_times(sim, scmd)
+        timed_samples = f_n
+        if f_n < MIN_KERNEL_SAMPLES:
+            # too few sampled launches in that call (one per graph replay):
+            # add replays of the same graphs
+            for _ in range(MIN_KERNEL_SAMPLES - f_n):
+                sim.step(steps)
+            f_ms, f_n, d_ms, d_n = _kernel_times(sim, scmd)
         scmd.scmd_set_profiling(sim.ctx, False)
         e = sim.energy()
         # with a cutoff the algorithmic pairs are those closer than rc: one
@@ -111,13 +143,16 @@ def time_gpu(w, steps: int, warmup: int, tuning=None):
         pairs_rc = None
         if w.rc > 0:
             pairs_rc = sum(int(sim.rdf(k, w.rc, 1)[0][0]) for k in range(sim.nclusters)) // 2
-        T = [sim.temperature(k)[0] for k in range(min(sim.nclusters, 1))]
+        T = sim.temperature(0)[0]
+        state = None
+        if keep_state:
+            state = {"pos": sim.positions(), "forces": sim.forces(),
+                     "epot": [sim.energy(k)[0] for k in range(sim.nclusters)]}
     finally:
         sim.close()
     sizes = w.sizes()
     natoms = int(sizes.sum())
     pairs = _pairs(sizes)
-    cut = w.rc > 0
     res = {
         "workload": w.name,
         "precision": w.precision,
@@ -126,15 +161,17 @@ def time_gpu(w, steps: int, warmup: int, tuning=None):
         "steps": steps,
         "seconds": dt,
         "ms_per_step": 1e3 * dt / steps,
+        "ms_per_step_with_profiling_events": 1e3 * dt_prof / steps,
         "atom_steps_per_s": natoms * steps / dt,
         "force_ms_per_launch": f_ms,
-        "force_launches_timed": f_n,
+        "force_launches_sampled": f_n,
+        "force_launches_sampled_in_profiled_call": timed_samples,
         "density_ms_per_launch": d_ms,
-        "density_launches_timed": d_n,
+        "density_launches_sampled": d_n,
         "final_energy_eV": e[2],
-        "final_T_K": T[0] if T else None,
+        "final_T_K": T,
     }
-    if cut:
+    if w.rc > 0:
         pairs = pairs_rc
         res["pairs_within_rc"] = pairs_rc
     res["pair_interactions_per_s"] = pairs * steps / dt
@@ -155,48 +192,120 @@ def time_gpu(w, steps: int, warmup: int, tuning=None):
     if len(sweeps) > 1:
         name, _, ach = sweeps[1]
         res["other_sweep_roofline"] = {"kernel": name, "achieved": ach, "frac": ach / PEAK_FP64_TFLOPS}
+    if state is not None:
+        res["state"] = state
     return res
 
 
+def mixed_error(w, state, nthreads: int, max_clusters: int = 4, sample: int = 64):
+    """Force and energy error of a mixed-precision run against the FP64
+    oracle at the run's final GPU positions: force relative norm error and
+    worst per-atom error (|dF_i| / max(|F_i|, F_rms)) over a fixed sample of
+    atoms, energy relative error of the cluster's potential energy.  Batches:
+    the smallest, the largest and two middle clusters."""
+    import oracle
+    sizes = w.sizes()
+    order = np.argsort(sizes, kind="stable")
+    picks = sorted(set(int(order[int(q * (len(order) - 1))]) for q in np.linspace(0, 1, max_clusters)))
+    out = {"clusters": [], "sample_atoms_per_cluster": sample}
+    worst = [0.0, 0.0, 0.0]
+    for k in picks:
+        a, b = int(w.offsets[k]), int(w.offsets[k + 1])
+        pos, f = state["pos"][a:b], state["forces"][a:b]
+        idx = np.sort(np.random.default_rng(k).choice(b - a, min(sample, b - a), replace=False))
+        f_ref, _ = oracle.forces_subset(pos, idx, nthreads=nthreads)
+        frms = np.sqrt(np.mean(np.sum(f ** 2, axis=1)))
+        fn = float(np.linalg.norm(f[idx] - f_ref) / np.linalg.norm(f_ref))
+        fw = float(np.max(np.linalg.norm(f[idx] - f_ref, axis=1) /
+                          np.maximum(np.linalg.norm(f_ref, axis=1), frms)))
+        e_ref = oracle.energy(pos, nthreads=nthreads)
+        ee = float(abs(state["epot"][k] - e_ref) / abs(e_ref))
+        out["clusters"].append({"cluster": k, "atoms": b - a, "force_rel_norm": fn, "force_worst_atom": fw,
+                                "energy_rel": ee})
+        worst = [max(worst[0], fn), max(worst[1], fw), max(worst[2], ee)]
+    out["force_rel_norm_max"], out["force_worst_atom_max"], out["energy_rel_max"] = worst
+    return out
+
+
 def cpu_baseline(w, budget_s: float):
-    """Time the FP64 oracle on the host cores on a bounded sample of the workload."""
+    """Time the FP64 oracle on the host cores on a bounded sample of the
+    workload: whole velocity-Verlet steps when one fits the budget, else one
+    force evaluation (the pair work of a step; the step's O(N) kick and drift
+    are negligible beside it), on all cores; then one core on the atoms
+    nearest the centre of the largest cluster, converted through its
+    pair-interaction rate (an all-pairs step costs the same per pair at any
+    size)."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    th = w.thermostat[0]
-    pos, vel = w.pos, w.vel
-    # one untimed step builds the initial forces
-    r, v, f, _ = oracle.vv_run(pos, vel, 1, dt=w.dt, thermostat=th, nthreads=threads, with_log=False)
-    steps, t_used = 0, 0.0
-    while t_used < budget_s:
-        t0 = time.perf_counter()
-        r, v, f, _ = oracle.vv_run(r, v, 1, dt=w.dt, thermostat=th, force=f, step0=1 + steps, nthreads=threads,
-                                   with_log=False)
-        t_used += time.perf_counter() - t0
-        steps += 1
+    sizes = w.sizes()
+    k = int(np.argmax(sizes))
+    pos, vel = w.cluster(k)
+    th = w.thermostat[k]
     n = len(pos)
-    # single core, as the paper compares against one CPU core
+    pairs_cluster = n * (n - 1) / 2
     t0 = time.perf_counter()
-    oracle.vv_run(r, v, 1, dt=w.dt, thermostat=th, force=f, nthreads=1, with_log=False)
+    f, _, _ = oracle.forces(pos, nthreads=threads)
+    t_eval = time.perf_counter() - t0
+    steps, t_steps = 0, 0.0
+    if t_eval < budget_s / 3:
+        r, v = pos, vel
+        while t_steps < budget_s:
+            t0 = time.perf_counter()
+            r, v, f, _ = oracle.vv_run(r, v, 1, dt=w.dt, thermostat=th, force=f, step0=steps, nthreads=threads,
+                                       with_log=False)
+            t_steps += time.perf_counter() - t0
+            steps += 1
+        rate_pairs = pairs_cluster * steps / t_steps
+        sample = (f"{steps} whole velocity-Verlet steps of cluster {k} ({n} atoms) of the {w.name} workload, "
+                  f"{t_steps:.1f} s on {threads} threads")
+    else:
+        rate_pairs = pairs_cluster / t_eval
+        sample = (f"one force evaluation (density and force sweeps: the pair work of one step) of cluster {k} "
+                  f"({n} atoms) of the {w.name} workload, {t_eval:.1f} s on {threads} threads")
+    # one core: the atoms nearest the cluster's centre, a compact sub-cluster
+    # sized for a few seconds
+    m = min(n, 4000)
+    sub = pos[np.argsort(np.sum((pos - pos.mean(axis=0)) ** 2, axis=1), kind="stable")[:m]]
+    t0 = time.perf_counter()
+    oracle.forces(sub, nthreads=1)
     t1 = time.perf_counter() - t0
+    rate1 = m * (m - 1) / 2 / t1
+    # atom-steps/s of the whole workload at the measured pair rate
+    total_pairs = _pairs(sizes)
+    natoms = int(sizes.sum())
     return {
-        "value": n * steps / t_used,
+        "value": rate_pairs * natoms / total_pairs,
         "unit": "atom-steps/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"{steps} velocity-Verlet steps of the {w.name} workload ({n} atoms) after one untimed step",
-        "single_core_atom_steps_per_s": n / t1,
+        "sample": sample + "; atom-steps/s of the whole workload = that pair rate x atoms / pairs per step",
+        "pair_interactions_per_s": rate_pairs,
+        "compiler": ORACLE_FLAGS,
+        "single_core": {"atom_steps_per_s": rate1 * natoms / total_pairs, "pair_interactions_per_s": rate1,
+                        "sample": f"one force evaluation of the {m} atoms nearest the centre of cluster {k}, "
+                                  f"{t1:.2f} s on 1 thread"},
     }
+
+
+FORMS = [("c2_fp64_ni2243", "ni2243_cooling", None), ("c2_mixed_ni2243", "ni2243_cooling", "mixed"),
+         ("c3_allpairs_fp64_ni48077", "ni48077_allpairs", None), ("allpairs_fp64_ni50000", "ni50000_allpairs", None),
+         ("c4_mixed_ni15000", "ni15000_mixed", None), ("c4_fp64_ni15000", "ni15000_fp64", None),
+         ("c5_batched_fp64_256", "batch256", None), ("c5_batched_mixed_256", "batch256_mixed", None),
+         ("c3_cell_fp64_ni48077", "ni48077_cell", None),
+         ("langevin_fp64_ni2243", "ni2243_langevin", None), ("langevin_batched_fp64_256", "batch256_langevin", None)]
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="ni2243_cooling")
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=64)
+    ap.add_argument("--workload", default="ni48077_allpairs")
     ap.add_argument("--no-forms", action="store_true", help="skip the extra forms")
+    ap.add_argument("--forms", default=None, help="comma-separated subset of the extra forms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-error", action="store_true", help="skip the mixed forms' oracle error")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--tuning", default=None,
                     help="JSON launch-shape override for the main workload, e.g. '{\"pairs\": 2, \"ipt\": 8}'")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -210,11 +319,12 @@ def main(argv=None):
               "multi-GPU sharding is a design note, not a code path", file=sys.stderr)
         return 2
 
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     w = _workload(args.workload)
     print(f"[bench] {w.name}: {w.n_atoms} atoms, {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
           flush=True)
-    main_res = time_gpu(w, args.steps, args.warmup, tuning=json.loads(args.tuning) if args.tuning else None)
-    # the committed counters are those of force-sweep kernels
+    tuning = json.loads(args.tuning) if args.tuning else None
+    main_res = time_gpu(w, args.steps, args.warmup, tuning=tuning, keep_state=w.precision == "mixed")
     if main_res.get("roofline") is not None and main_res["roofline"]["kernel"] == "force sweep":
         main_res["roofline"]["traffic"] = measured_traffic(args.workload)
     print(f"[bench] {main_res['atom_steps_per_s']:.4e} atom-steps/s, {main_res['ms_per_step']:.4f} ms/step",
@@ -233,27 +343,27 @@ def main(argv=None):
 
     forms = {}
     if not args.no_forms:
-        plan = [("fp64_ni2243", None, None), ("mixed_ni2243", "ni2243_cooling", "mixed"),
-                ("allpairs_fp64_ni48077", "ni48077_allpairs", None), ("allpairs_fp64_ni50000", "ni50000_allpairs", None),
-                ("mixed_ni15000", "ni15000_mixed", None), ("fp64_ni15000", "ni15000_fp64", None),
-                ("batched_fp64_256", "batch256", None), ("batched_mixed_256", "batch256_mixed", None),
-                ("cell_fp64_ni48077", "ni48077_cell", None),
-                ("langevin_fp64_ni2243", "ni2243_langevin", None), ("langevin_batched_fp64_256", "batch256_langevin", None)]
-        for key, name, prec in plan:
-            if name is None:
+        wanted = set(args.forms.split(",")) if args.forms else None
+        for key, name, prec in FORMS:
+            if wanted is not None and key not in wanted:
+                continue
+            if name == args.workload and prec is None:
                 forms[key] = {k: main_res[k] for k in ("atom_steps_per_s", "pair_interactions_per_s", "ms_per_step")}
+                forms[key]["headline"] = True
                 continue
             try:
                 fw = _workload(name)
                 if prec:
                     fw.precision = prec
-                n = fw.n_atoms
-                steps = max(20, min(2000, int(2e10 / max(1, _pairs(fw.sizes())))))
-                print(f"[bench] form {key}: {n} atoms, {steps} steps", file=sys.stderr, flush=True)
-                r = time_gpu(fw, steps, min(20, steps))
+                steps = max(32, min(2000, int(2e10 / max(1, _pairs(fw.sizes())))))
+                print(f"[bench] form {key}: {fw.n_atoms} atoms, {steps} steps", file=sys.stderr, flush=True)
+                r = time_gpu(fw, steps, min(64, steps), keep_state=fw.precision == "mixed" and not args.no_error)
                 forms[key] = {k: r[k] for k in ("atom_steps_per_s", "pair_interactions_per_s", "ms_per_step",
                                                 "force_ms_per_launch", "density_ms_per_launch", "roofline",
                                                 "steps", "n_atoms", "n_clusters", "pairs_within_rc") if k in r}
+                if "state" in r:
+                    print(f"[bench] form {key}: error against the FP64 oracle", file=sys.stderr, flush=True)
+                    forms[key]["error_vs_fp64_oracle"] = mixed_error(fw, r["state"], threads)
             except Exception as exc:  # a form that is not available is reported, not fatal
                 forms[key] = {"error": str(exc)}
 
@@ -280,11 +390,14 @@ def main(argv=None):
                    "pairs_per_step": main_res.get("pairs_per_step"), "parallelism": "single_gpu"},
         "pair_interactions_per_s": main_res.get("pair_interactions_per_s"),
         "roofline": main_res.get("roofline"),
-        "kernel_timing": {k: main_res.get(k) for k in ("force_ms_per_launch", "force_launches_timed",
-                                                       "density_ms_per_launch")},
+        "kernel_timing": {k: main_res.get(k) for k in (
+            "force_ms_per_launch", "force_launches_sampled", "force_launches_sampled_in_profiled_call",
+            "density_ms_per_launch", "ms_per_step_with_profiling_events")},
         "cpu_baseline": cpu,
         "forms": forms,
     }
+    if "state" in main_res and not args.no_error:
+        out["error_vs_fp64_oracle"] = mixed_error(w, main_res["state"], threads)
     print(json.dumps(out))
     return 0
 

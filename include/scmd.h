@@ -214,14 +214,20 @@ int scmd_set_langevin(scmd_ctx *ctx, int cluster, double T_start_K, double T_end
 /* Override the sweep launch shape (NULL restores defaults). */
 int scmd_set_tuning(scmd_ctx *ctx, const scmd_tuning *tuning);
 
-/* Evaluate rho, forces, energies and temperature at the current positions,
- * without moving atoms.  Enqueued on the context stream; synchronises and
- * returns SCMD_ENONFINITE when an energy is not finite. */
+/* Evaluate rho_i (Sec. 2.1, Eq. (rho)), the forces -grad U of Eq. (SC) and
+ * the energies, by the paper's two sweeps over all pairs (Sec. 2,
+ * "Computational approach": every density first, then the forces), and the
+ * temperature, at the current positions, without moving atoms.  Enqueued on
+ * the context stream; synchronises and returns SCMD_ENONFINITE when an energy
+ * is not finite. */
 int scmd_compute(scmd_ctx *ctx);
 
-/* Advance every cluster by nsteps >= 0 velocity-Verlet steps (forces at the
- * initial positions are computed first if needed).  Steps are replayed from
- * captured HIP graphs.  Waits for completion and returns SCMD_ENONFINITE
+/* Advance every cluster by nsteps >= 0 velocity-Verlet steps (Sec. 2,
+ * "Computational approach": per step a density sweep and a force sweep over
+ * all pairs, integrated with velocity-Verlet; forces at the initial
+ * positions are computed first if needed).  Steps are replayed from captured
+ * HIP graphs: a 32-step graph and a graph of the remainder (nsteps mod 32),
+ * each kept for later calls.  Waits for completion and returns SCMD_ENONFINITE
  * if an energy became non-finite during these steps (the state is then
  * undefined). */
 int scmd_step(scmd_ctx *ctx, int64_t nsteps);
@@ -237,11 +243,16 @@ int scmd_synchronize(scmd_ctx *ctx);
 int scmd_get_step(scmd_ctx *ctx, int64_t *step);
 
 /* Energies of the current state of one cluster (cluster = -1: sum over all):
- * out3[0] = E_pot, out3[1] = E_kin, out3[2] = E_pot + E_kin, eV.  Valid after
- * scmd_compute or scmd_step. */
+ * out3[0] = E_pot = U of Sec. 2.1, Eq. (SC) (with the shifted powers when
+ * rc > 0), out3[1] = E_kin = sum m v^2 / 2, out3[2] = E_pot + E_kin, eV (the
+ * paper follows the total energy per atom of its runs, Sec. 3).  Valid after
+ * scmd_compute or scmd_step; out3 is host memory of 3 doubles. */
 int scmd_get_energy(scmd_ctx *ctx, int cluster, double out3[3]);
 
-/* Temperature (K) and degrees of freedom of one cluster's current state. */
+/* Temperature T = 2 E_kin / (ndof k_B) (K) of one cluster's current state
+ * and its degrees of freedom (3N - 6 for a free cluster, 3N in a Langevin
+ * bath); the paper plots its runs' energy against this temperature (Sec. 3).
+ * T_K (host) required, ndof may be NULL. */
 int scmd_get_temperature(scmd_ctx *ctx, int cluster, double *T_K, int64_t *ndof);
 
 /* Observables along a trajectory (the paper follows the energy per atom and
@@ -265,9 +276,11 @@ int scmd_set_sampling(scmd_ctx *ctx, int64_t every, int capacity);
 int scmd_get_samples(scmd_ctx *ctx, int cluster, double *out, int max_samples, int *n_out, int64_t *recorded);
 
 /* Copy current state to host arrays of offsets[n_clusters] x 3 doubles
- * (density: offsets[n_clusters] doubles).  Velocities include any pending
- * thermostat factor.  Forces and density are those of the current positions
- * (valid after scmd_compute or scmd_step). */
+ * (density: offsets[n_clusters] doubles), caller-owned, row-major x y z.
+ * Velocities include any pending thermostat factor.  Forces (eV/A, -grad U of
+ * Sec. 2.1 Eq. (SC)) and density (rho_i of Eq. (rho), dimensionless) are
+ * those of the current positions (valid after scmd_compute or scmd_step,
+ * else SCMD_ESTATE). */
 int scmd_get_positions(scmd_ctx *ctx, double *out);
 int scmd_get_velocities(scmd_ctx *ctx, double *out);
 int scmd_get_forces(scmd_ctx *ctx, double *out);
@@ -339,11 +352,13 @@ int scmd_set_state(scmd_ctx *ctx, const void *buf, size_t bytes);
 
 /* Record device time per launch of the pair sweeps during subsequent
  * scmd_step / scmd_compute calls: HIP events on the context stream around
- * every eager launch, and inside each captured graph around the sweeps of its
- * last step (event nodes between graph kernels cost a few microseconds, so a
- * graph is sampled once per replay; the sample of the last replay of each
- * scmd_step call is kept).  enable = 0 stops recording and resets the
- * averages. */
+ * every eager launch (scmd_compute, the first force evaluation of a run),
+ * and inside each captured graph (the 32-step graph and the graph of a run's
+ * remainder) around the sweeps of its second-to-last step (event nodes
+ * between graph kernels cost a few microseconds, so a graph is sampled once
+ * per replay; the sample of its last replay in each scmd_step call is kept).
+ * Changing the setting re-captures the graphs; enable = 0 stops recording;
+ * every call resets the averages. */
 int scmd_set_profiling(scmd_ctx *ctx, int enable);
 
 /* Average device milliseconds per launch of a kernel class over the launches

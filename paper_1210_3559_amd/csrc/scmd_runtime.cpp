@@ -136,16 +136,24 @@ struct scmd_ctx {
     int64_t step = 0;
 
     // graphs
-    hipGraphExec_t graph = nullptr;
-    int graph_profiled = 0;
+    // slot 0: kGraphSteps steps; slot 1: the remainder of the last run
+    // length that was not a multiple of kGraphSteps
+    struct GraphSlot {
+        hipGraphExec_t exec = nullptr;
+        int64_t len = 0;
+        int profiled = 0;
+        std::vector<int> ev;  // profiling events captured in the graph
+        bool unread = false;  // replayed since its events were last read
+    };
+    GraphSlot graphs[2];
+    std::vector<int> *ev_capture = nullptr;  // event list of the graph being captured
 
     // profiling
     int profiling = 0;
     bool capture_sample = false;  // the step being captured carries event nodes
     bool graph_events_ok = true;
     std::vector<EvPair> evs;
-    std::vector<int> ev_free, ev_pending, ev_graph;
-    bool graph_unread = false;
+    std::vector<int> ev_free, ev_pending;
     double prof_ms[SCMD_KERNEL_COUNT] = {0, 0};
     int64_t prof_n[SCMD_KERNEL_COUNT] = {0, 0};
 };
@@ -209,12 +217,19 @@ PotConst make_pot(const scmd_sc_params &p) {
     return pc;
 }
 
+void drop_graph_slot(scmd_ctx *c, int slot) {
+    scmd_ctx::GraphSlot &g = c->graphs[slot];
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    g.len = 0;
+    for (int i : g.ev) c->ev_free.push_back(i);
+    g.ev.clear();
+    g.unread = false;
+}
+
 void drop_graph(scmd_ctx *c) {
-    if (c->graph) (void)hipGraphExecDestroy(c->graph);
-    c->graph = nullptr;
-    for (int i : c->ev_graph) c->ev_free.push_back(i);
-    c->ev_graph.clear();
-    c->graph_unread = false;
+    drop_graph_slot(c, 0);
+    drop_graph_slot(c, 1);
 }
 
 bool ready(scmd_ctx *c) { return c->have_clusters && c->have_pot && c->have_integ; }
@@ -254,9 +269,11 @@ void harvest_events(scmd_ctx *c) {
         c->ev_free.push_back(idx);
     }
     c->ev_pending.clear();
-    if (c->graph_unread) {
-        for (int idx : c->ev_graph) read(idx);
-        c->graph_unread = false;
+    for (auto &g : c->graphs) {
+        if (g.unread) {
+            for (int idx : g.ev) read(idx);
+            g.unread = false;
+        }
     }
 }
 
@@ -696,7 +713,7 @@ hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int adv
     if (ev >= 0) {
         e = record(c->evs[ev].b, s, capturing);
         if (e != hipSuccess) return e;
-        (capturing ? c->ev_graph : c->ev_pending).push_back(ev);
+        (capturing ? *c->ev_capture : c->ev_pending).push_back(ev);
     }
     return hipSuccess;
 }
@@ -790,33 +807,41 @@ hipError_t enqueue_run(scmd_ctx *c, hipStream_t s, bool capturing, int64_t nstep
     return hipSuccess;
 }
 
-int ensure_graph(scmd_ctx *c) {
-    if (c->graph && c->graph_profiled == c->profiling) return SCMD_OK;
-    drop_graph(c);
+// Graph slot `slot` holding runs of `len` steps, captured when missing,
+// of another length or taken with another profiling setting.
+int ensure_graph(scmd_ctx *c, int slot, int64_t len) {
+    scmd_ctx::GraphSlot &G = c->graphs[slot];
+    if (G.exec && G.len == len && G.profiled == c->profiling) return SCMD_OK;
+    // an earlier replay of the graph being replaced may still run
+    if (G.exec) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    drop_graph_slot(c, slot);
     hipGraph_t g = nullptr;
+    c->ev_capture = &G.ev;
     HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enqueue_run(c, c->cap_stream, true, kGraphSteps);
+    hipError_t e = enqueue_run(c, c->cap_stream, true, len);
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+    c->ev_capture = nullptr;
     if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
-        for (int i : c->ev_graph) c->ev_free.push_back(i);
-        c->ev_graph.clear();
+        for (int i : G.ev) c->ev_free.push_back(i);
+        G.ev.clear();
         if (c->profiling && c->graph_events_ok) {
             // event records inside capture unsupported: profile eagerly instead
             c->graph_events_ok = false;
             (void)hipGetLastError();
-            return ensure_graph(c);
+            return ensure_graph(c, slot, len);
         }
         return fail(c, SCMD_EDEVICE, std::string("graph capture failed: ") +
                                          hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    hipError_t e3 = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    hipError_t e3 = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e3 != hipSuccess) {
-        c->graph = nullptr;
+        G.exec = nullptr;
         return fail(c, SCMD_EDEVICE, std::string("graph instantiate failed: ") + hipGetErrorString(e3));
     }
-    c->graph_profiled = c->profiling;
+    G.len = len;
+    G.profiled = c->profiling;
     return SCMD_OK;
 }
 
@@ -834,19 +859,28 @@ int sync_and_check(scmd_ctx *c) {
     return SCMD_OK;
 }
 
-// nsteps steps as graph replays plus an eager remainder; every replay and
-// run ends with the per-cluster finalize, so the state is complete after it.
+// nsteps steps as replays of the kGraphSteps-step graph plus one replay of
+// a graph of the remainder (kept for the next run of the same remainder);
+// every replay ends with the per-cluster finalize, so the state is complete
+// after it.  Eager launches only when profiling events cannot be captured.
 int enqueue_chunk(scmd_ctx *c, int64_t nsteps) {
     const bool use_graph = !(c->profiling && !c->graph_events_ok);
     int64_t full = use_graph ? nsteps / kGraphSteps : 0;
     int64_t rem = nsteps - full * kGraphSteps;
     if (full > 0) {
-        int rc = ensure_graph(c);
+        int rc = ensure_graph(c, 0, kGraphSteps);
         if (rc != SCMD_OK) return rc;
-        for (int64_t r = 0; r < full; ++r) HIP_TRY(c, hipGraphLaunch(c->graph, c->stream));
-        c->graph_unread = c->profiling != 0;
+        for (int64_t r = 0; r < full; ++r) HIP_TRY(c, hipGraphLaunch(c->graphs[0].exec, c->stream));
+        c->graphs[0].unread = c->profiling != 0;
     }
-    if (rem > 0) HIP_TRY(c, enqueue_run(c, c->stream, false, rem));
+    if (rem > 0 && use_graph) {
+        int rc = ensure_graph(c, 1, rem);
+        if (rc != SCMD_OK) return rc;
+        HIP_TRY(c, hipGraphLaunch(c->graphs[1].exec, c->stream));
+        c->graphs[1].unread = c->profiling != 0;
+    } else if (rem > 0) {
+        HIP_TRY(c, enqueue_run(c, c->stream, false, rem));
+    }
     c->step += nsteps;
     return SCMD_OK;
 }

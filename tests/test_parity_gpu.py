@@ -377,11 +377,18 @@ def test_profiling_records_sweep_times():
     w = inputs.c2_cooling()
     with scmd.Simulation.from_workload(w) as sim:
         scmd.scmd_set_profiling(sim.ctx, True)
+        # the eager first force evaluation, then one sample per captured
+        # graph per call: the 32-step graph (replayed twice) and the graph
+        # of the 5-step remainder
         sim.step(64 + 5)
         ms_f, n_f = scmd.scmd_get_kernel_time(sim.ctx, scmd.SCMD_KERNEL_FORCE)
         ms_d, n_d = scmd.scmd_get_kernel_time(sim.ctx, scmd.SCMD_KERNEL_DENSITY)
+        assert (n_f, n_d) == (3, 3)
+        sim.step(64 + 5)  # both graphs reused
+        ms_f, n_f = scmd.scmd_get_kernel_time(sim.ctx, scmd.SCMD_KERNEL_FORCE)
+        ms_d, n_d = scmd.scmd_get_kernel_time(sim.ctx, scmd.SCMD_KERNEL_DENSITY)
     print(f"[prof] force {ms_f:.4f} ms x{n_f}, density {ms_d:.4f} ms x{n_d}", flush=True)
-    assert n_f >= 5 and n_d >= 5
+    assert (n_f, n_d) == (5, 5)
     assert 0.0 < ms_f < 100.0 and 0.0 < ms_d < 100.0
 
 
