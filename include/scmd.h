@@ -307,6 +307,21 @@ int scmd_get_forces_device(scmd_ctx *ctx, double *dev_out);
 int scmd_rdf(scmd_ctx *ctx, int cluster, double r_select, double dr, int nbins, uint64_t *counts,
              int64_t *n_ref);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops): scmd_rdf without any allocation and without
+ * waiting.  The histogram of the cluster's current positions, defined as for
+ * scmd_rdf, is ADDED on the context stream to dev_counts[nbins] (caller
+ * device memory, uint64) and the number of reference atoms to *dev_n_ref
+ * (caller device memory, int64); the call returns once the work is enqueued
+ * and the caller synchronises (e.g. scmd_synchronize) before reading.  The
+ * reference-atom list lives in a fixed device array of the library (4 MiB +
+ * 256 bytes per GPU, held until the process ends) shared by every context on
+ * that GPU: clusters above 1,048,576 atoms return SCMD_EINVAL, and calls that
+ * overlap on one GPU (other streams, other threads) race on that array.
+ * Other errors as scmd_rdf; device pointers are not checked. */
+int scmd_rdf_noalloc(scmd_ctx *ctx, int cluster, double r_select, double dr, int nbins, uint64_t *dev_counts,
+                     int64_t *dev_n_ref);
+
 /* Frames for the self-diffusion coefficient (Sec. 3, "Diffusion coefficient
  * as a fingerprint of solidification phase transition").  scmd_set_frames
  * gives cluster `cluster` a device store that keeps its last `capacity`

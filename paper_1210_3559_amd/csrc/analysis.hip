@@ -116,6 +116,11 @@ __global__ void k_fill_u64(unsigned long long *p, int n) {
     if (i < n) p[i] = 0ull;
 }
 
+// Adds the number of reference atoms to a 64-bit device total.
+__global__ void k_add_nref(const int *__restrict__ nref, long long *__restrict__ total) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) total[0] += (long long)nref[0];
+}
+
 
 // ---------------------------------------------------------------------------
 // Self-diffusion coefficient of the central atoms (Sec. 3, "Diffusion
@@ -335,9 +340,9 @@ __global__ void k_store_frame(const double4 *__restrict__ rp, int off, int n, do
 }  // namespace
 
 hipError_t launch_rdf(const double4 *rp, int off, int n, double r_select, double dr, int nbins, int32_t *refs,
-                      int *nref, unsigned long long *counts, hipStream_t s) {
+                      int *nref, unsigned long long *counts, bool clear, long long *nref_total, hipStream_t s) {
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_fill_u64, dim3((nbins + 255) / 256), dim3(256), 0, s, counts, nbins);
+    if (clear) hipLaunchKernelGGL(k_fill_u64, dim3((nbins + 255) / 256), dim3(256), 0, s, counts, nbins);
     hipLaunchKernelGGL(k_rdf_select, dim3(1), dim3(kSelBlock), 0, s, rp, off, n, r_select, refs, nref);
     if (n > 0) {
         const size_t lds = (size_t)nbins * sizeof(unsigned int);
@@ -351,6 +356,7 @@ hipError_t launch_rdf(const double4 *rp, int off, int n, double r_select, double
         hipLaunchKernelGGL(k_rdf_hist, dim3((n + kRefsPerBlock - 1) / kRefsPerBlock), dim3(kHistBlock), lds, s, rp,
                            off, n, refs, nref, dr, nbins, counts);
     }
+    if (nref_total) hipLaunchKernelGGL(k_add_nref, dim3(1), dim3(64), 0, s, nref, nref_total);
     return hipGetLastError();
 }
 

@@ -236,10 +236,11 @@ hipError_t launch_aos_from4(const double4 *src, double *dst, int natoms, hipStre
 hipError_t launch_sample(const ClusterState *st, int nclusters, double *ring, int slot, int64_t step, hipStream_t s);
 
 // Pair-distance histogram of the atoms [off, off + n) (analysis.hip): refs
-// (n entries) and nref receive the reference atoms, counts (nbins) is
-// cleared and filled.
+// (n entries) and nref receive the reference atoms; counts (nbins) is
+// cleared first when `clear`, then the pairs are added to it; nref_total,
+// when not null, has the number of reference atoms added to it.
 hipError_t launch_rdf(const double4 *rp, int off, int n, double r_select, double dr, int nbins, int32_t *refs,
-                      int *nref, unsigned long long *counts, hipStream_t s);
+                      int *nref, unsigned long long *counts, bool clear, long long *nref_total, hipStream_t s);
 
 // Frame store of the diffusion coefficient (analysis.hip): copy the atoms
 // [off, off + n) of rp to dst (n entries).

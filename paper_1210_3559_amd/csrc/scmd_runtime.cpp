@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -22,6 +23,34 @@ using namespace scmd;
 namespace {
 
 thread_local std::string g_create_error;
+
+// Fixed device memory of scmd_rdf_noalloc (the reference-atom list of the
+// pair-distance histogram and its count): kScratchRefs 32-bit indices plus
+// one 256-byte block for the count.  Every context on a device shares that
+// device's copy.  Host code never passes the array itself to a kernel: each
+// device's address comes from hipGetSymbolAddress (g_scratch).
+constexpr int kScratchRefs = 1 << 20;
+constexpr size_t kScratchBytes = (size_t)kScratchRefs * sizeof(int32_t) + 256;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch[kMaxDevices] = {};
+
+// Address of the scratch array on `device` (which must be current), looked up
+// once per device.
+hipError_t scratch_address(int device, void **out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[device] = p;
+    }
+    *out = g_scratch[device];
+    return hipSuccess;
+}
 
 constexpr int kGraphSteps = 32;  // steps per captured graph
 
@@ -100,6 +129,7 @@ struct scmd_ctx {
         DevBuf<double4> buf;
     };
     std::vector<FrameStore> frames;
+    void *scratch = nullptr;  // this device's fixed scratch array (scmd_rdf_noalloc)
     DevBuf<double> diff_seg;  // per-segment coefficients, then the mean
     DevBuf<int> diff_ncentral;
     int *h_flag = nullptr;  // pinned
@@ -1081,6 +1111,15 @@ int scmd_create(scmd_ctx **out, int device, void *hip_stream) {
         scmd_destroy(c);
         return SCMD_EDEVICE;
     }
+    // the device's scratch array (scmd_rdf_noalloc), looked up while the
+    // device is current
+    void *scr = nullptr;
+    if ((e = scratch_address(device, &scr)) != hipSuccess) {
+        g_create_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        scmd_destroy(c);
+        return SCMD_EDEVICE;
+    }
+    c->scratch = scr;
     *out = c;
     return SCMD_OK;
 }
@@ -1517,7 +1556,7 @@ int scmd_rdf(scmd_ctx *ctx, int cluster, double r_select, double dr, int nbins, 
         HIP_TRY(ctx, ctx->rdf_nref.ensure(1));
         HIP_TRY(ctx, ctx->rdf_counts.ensure(nbins));
         HIP_TRY(ctx, launch_rdf(ctx->rp.p, off, n, r_select, dr, nbins, ctx->rdf_refs.p, ctx->rdf_nref.p,
-                                ctx->rdf_counts.p, ctx->stream));
+                                ctx->rdf_counts.p, true, nullptr, ctx->stream));
         std::vector<unsigned long long> h(nbins);
         int nr = 0;
         HIP_TRY(ctx, hipMemcpyAsync(h.data(), ctx->rdf_counts.p, nbins * sizeof(unsigned long long),
@@ -1528,6 +1567,29 @@ int scmd_rdf(scmd_ctx *ctx, int cluster, double r_select, double dr, int nbins, 
         *n_ref += nr;
         return SCMD_OK;
     })
+}
+
+int scmd_rdf_noalloc(scmd_ctx *ctx, int cluster, double r_select, double dr, int nbins, uint64_t *dev_counts,
+                     int64_t *dev_n_ref) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!ctx->have_clusters) return fail(ctx, SCMD_ESTATE, "init_clusters first");
+    if (cluster < 0 || cluster >= ctx->nclusters) return fail(ctx, SCMD_EINVAL, "cluster index out of range");
+    if (!(dr > 0.0) || !std::isfinite(dr)) return fail(ctx, SCMD_EINVAL, "need a finite dr > 0");
+    if (!std::isfinite(r_select)) return fail(ctx, SCMD_EINVAL, "r_select must be finite");
+    if (nbins < 1 || nbins > kRdfMaxBins) return fail(ctx, SCMD_EINVAL, "nbins must be in [1, 32768]");
+    if (!dev_counts || !dev_n_ref) return fail(ctx, SCMD_EINVAL, "dev_counts or dev_n_ref is NULL");
+    const int off = (int)ctx->offsets[cluster];
+    const int n = (int)(ctx->offsets[cluster + 1] - ctx->offsets[cluster]);
+    if (n > kScratchRefs)
+        return fail(ctx, SCMD_EINVAL, "cluster larger than the fixed scratch array (1048576 atoms)");
+    if (!ctx->scratch) return fail(ctx, SCMD_EDEVICE, "no scratch address for this device");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    // scratch layout: the count in the first 256 bytes, then the references
+    int *nref = (int *)ctx->scratch;
+    int32_t *refs = (int32_t *)((unsigned char *)ctx->scratch + 256);
+    HIP_TRY(ctx, launch_rdf(ctx->rp.p, off, n, r_select, dr, nbins, refs, nref, (unsigned long long *)dev_counts,
+                            false, (long long *)dev_n_ref, ctx->stream));
+    return SCMD_OK;
 }
 
 int scmd_set_frames(scmd_ctx *ctx, int cluster, int capacity) {

@@ -46,7 +46,7 @@ EXPORTS = (
     "scmd_step", "scmd_step_async", "scmd_synchronize", "scmd_get_step", "scmd_get_energy",
     "scmd_get_temperature", "scmd_get_positions", "scmd_get_velocities", "scmd_get_forces", "scmd_get_density",
     "scmd_get_forces_device", "scmd_get_state", "scmd_set_state", "scmd_set_profiling", "scmd_get_kernel_time",
-    "scmd_set_sampling", "scmd_get_samples", "scmd_rdf", "scmd_set_frames", "scmd_record_frame",
+    "scmd_set_sampling", "scmd_get_samples", "scmd_rdf", "scmd_rdf_noalloc", "scmd_set_frames", "scmd_record_frame",
     "scmd_get_frame_count", "scmd_diffusion", "scmd_last_error",
 )
 
@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH):
         "scmd_get_density": (i32, [vp, dp]),
         "scmd_get_forces_device": (i32, [vp, vp]),
         "scmd_rdf": (i32, [vp, i32, dbl, dbl, i32, vp, ctypes.POINTER(i64)]),
+        "scmd_rdf_noalloc": (i32, [vp, i32, dbl, dbl, i32, vp, vp]),
         "scmd_set_frames": (i32, [vp, i32, i32]),
         "scmd_record_frame": (i32, [vp]),
         "scmd_get_frame_count": (i32, [vp, i32, ctypes.POINTER(i64)]),
@@ -303,6 +304,20 @@ def scmd_rdf(ctx, cluster: int, dr: float, nbins: int, r_select: float = 0.0, co
     _check(ctx, load().scmd_rdf(ctx, int(cluster), float(r_select), float(dr), int(nbins),
                                 out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nr)))
     return out, int(nr.value)
+
+
+def scmd_rdf_noalloc(ctx, cluster: int, dr: float, nbins: int, dev_counts, dev_n_ref, r_select: float = 0.0) -> None:
+    """Add the pair-distance histogram to device memory without allocating
+    or waiting: dev_counts is a contiguous 64-bit CUDA tensor of nbins
+    entries, dev_n_ref one of at least 1 entry (or raw device addresses)."""
+    def addr(x, need):
+        if hasattr(x, "data_ptr"):
+            if not x.is_cuda or not x.is_contiguous() or x.element_size() != 8 or x.numel() < need:
+                raise ValueError(f"need a contiguous 64-bit CUDA tensor of at least {need} entries")
+            return ctypes.c_void_p(x.data_ptr())
+        return ctypes.c_void_p(int(x))
+    _check(ctx, load().scmd_rdf_noalloc(ctx, int(cluster), float(r_select), float(dr), int(nbins),
+                                        addr(dev_counts, int(nbins)), addr(dev_n_ref, 1)))
 
 
 def scmd_set_frames(ctx, cluster: int, capacity: int) -> None:
