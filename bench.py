@@ -197,6 +197,13 @@ def time_gpu(w, steps: int, warmup: int, tuning=None, keep_state: bool = False):
     return res
 
 
+def autotune_pick(w):
+    """The autotuner's launch plan for this workload's cluster layout and
+    precision (None when the table has no entry: library defaults)."""
+    from paper_1210_3559_amd import autotune
+    return autotune.lookup(w.offsets, w.precision)
+
+
 def mixed_error(w, state, nthreads: int, max_clusters: int = 4, sample: int = 64):
     """Force and energy error of a mixed-precision run against the FP64
     oracle at the run's final GPU positions: force relative norm error and
@@ -357,10 +364,17 @@ def main(argv=None):
                     fw.precision = prec
                 steps = max(32, min(2000, int(2e10 / max(1, _pairs(fw.sizes())))))
                 print(f"[bench] form {key}: {fw.n_atoms} atoms, {steps} steps", file=sys.stderr, flush=True)
-                r = time_gpu(fw, steps, min(64, steps), keep_state=fw.precision == "mixed" and not args.no_error)
+                # batches run the launch plan the autotuner measured for them
+                # (paper_1210_3559_amd/tuning_cache.json)
+                tun = "auto" if fw.n_clusters > 1 else None
+                r = time_gpu(fw, steps, min(64, steps), tuning=tun,
+                             keep_state=fw.precision == "mixed" and not args.no_error)
+                if tun:
+                    r["tuning"] = autotune_pick(fw)
                 forms[key] = {k: r[k] for k in ("atom_steps_per_s", "pair_interactions_per_s", "ms_per_step",
                                                 "force_ms_per_launch", "density_ms_per_launch", "roofline",
-                                                "steps", "n_atoms", "n_clusters", "pairs_within_rc") if k in r}
+                                                "steps", "n_atoms", "n_clusters", "pairs_within_rc", "tuning")
+                              if k in r}
                 if "state" in r:
                     print(f"[bench] form {key}: error against the FP64 oracle", file=sys.stderr, flush=True)
                     forms[key]["error_vs_fp64_oracle"] = mixed_error(fw, r["state"], threads)

@@ -26,6 +26,7 @@ SHAPES = [(1, 4, 1), (2, 4, 1), (1, 2, 2), (2, 2, 2), (1, 1, 4), (2, 1, 4), (1, 
 TARGETS = [1, 512, 2048, 8192]
 ROW_WAVES = [4, 8, 16]
 ROW_TARGETS = [256, 512, 1024]  # workgroups per row sweep
+# measured on MI355X by `python -m paper_1210_3559_amd.autotune` and committed with the package
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 ARCH = "gfx950"
 
@@ -48,11 +49,7 @@ def tune(w, precision: str | None = None, budget_s: float = 0.25, shapes=SHAPES,
     precision = precision or w.precision
     pairs = float(np.sum(w.sizes().astype(np.float64) ** 2))
     table = []
-    candidates = [(dict(ipt=ipt, waves_i=wi, waves_j=wj, pairs=1), targets) for ipt, wi, wj in shapes]
-    if symmetric:
-        candidates += [(dict(ipt=ipt, pairs=2), targets) for ipt in (2, 4, 8)]
-    if row:
-        candidates += [(dict(waves_j=wv, pairs=3), ROW_TARGETS) for wv in ROW_WAVES]
+    candidates = candidate_plans(w.sizes(), shapes, targets, symmetric, row)
     for cand, tgts in candidates:
         for tgt in tgts:
             tun = dict(cand, target_items=tgt)
@@ -68,6 +65,27 @@ def tune(w, precision: str | None = None, budget_s: float = 0.25, shapes=SHAPES,
                       f"({pairs / dt / 1e9:.1f} G ordered pairs/s)", file=sys.stderr, flush=True)
     best = min(table, key=lambda r: r["ms_per_step"])
     return best["tuning"], table
+
+
+def candidate_plans(sizes, shapes=SHAPES, targets=TARGETS, symmetric: bool = True, row: bool = True):
+    """(tuning, work-splitting targets) pairs worth timing for clusters of
+    these sizes: row sweeps only where every cluster fits the LDS staging
+    (<= 4096 atoms) and the batch is small, one-sided shapes only for
+    clusters up to 16k atoms (beyond, they evaluate every pair twice and lose
+    to the symmetric sweeps by about 2x), symmetric sweeps always, with item
+    targets up to 16384 for large pair counts."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    nmax = int(sizes.max()) if len(sizes) else 0
+    pairs = float(np.sum(sizes.astype(np.float64) * (sizes - 1) / 2.0))
+    out = []
+    if nmax <= 16384:
+        out += [(dict(ipt=ipt, waves_i=wi, waves_j=wj, pairs=1), targets) for ipt, wi, wj in shapes]
+    if symmetric:
+        sym_targets = sorted(set(list(targets) + ([4096, 16384] if pairs > 1e8 else [])))
+        out += [(dict(ipt=ipt, pairs=2), sym_targets) for ipt in (2, 4, 8)]
+    if row and nmax <= 4096 and pairs <= 1e8:
+        out += [(dict(waves_j=wv, pairs=3), ROW_TARGETS) for wv in ROW_WAVES]
+    return out
 
 
 def load_cache(path: str = DEFAULT_CACHE) -> dict:

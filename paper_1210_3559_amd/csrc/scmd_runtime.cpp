@@ -522,9 +522,11 @@ int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
     {
         int64_t nmax = 0;
         for (int k = 0; k < c->nclusters; ++k) nmax = std::max<int64_t>(nmax, c->offsets[k + 1] - c->offsets[k]);
-        // Library choice (from the autotuner on MI355X): symmetric sweeps for
-        // batches and for clusters above 4096 atoms; IPT 4 and fine splitting
-        // for batches and very large clusters, IPT 2 in between.
+        // Library choice (from the autotuner on MI355X, its table committed
+        // with the Python package): symmetric sweeps for batches and for
+        // clusters above 4096 atoms; eight tiles per wavefront (fewest moves
+        // per pair) and fine splitting for large batches and very large
+        // clusters, two tiles in between.
         const bool allowed = c->neighbour == SCMD_ALLPAIRS && !c->pc.generic;
         const bool batch = c->nclusters > 1;
         // row sweeps: single clusters up to 4096 atoms, unless a one-sided
@@ -546,11 +548,11 @@ int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
         }
         c->sym = allowed && (c->tuning.pairs == 2 || (c->tuning.pairs == 0 && (batch || nmax > 4096)));
         if (c->sym) {
-            int ipt = nmax > 32768 ? 4 : 2;
+            int ipt = nmax > 32768 ? 8 : 2;
             int target = nmax > 32768 ? 8192 : 2048;
             if (batch) {
                 // about 32k pairs per work item, 512 to 8192 items
-                ipt = upairs >= 2e8 ? 4 : 2;
+                ipt = upairs >= 2e8 ? 8 : 2;
                 target = 512;
                 while (target < 8192 && target * 32768.0 * 1.5 < upairs) target *= 2;
             }

@@ -7,7 +7,7 @@ rate is kappa = 1/<t> (Eq. (rate2)), and its temperature dependence is fitted
 with ln(kappa * 1 ps) = a - b / (k_B T (T - T0)^2) (Eq. (rate3)).
 
     python -m paper_1210_3559_amd.kinetics --T 780 [--replicas 15]
-        [--max-ps 4000] [--out file.json]
+        [--max-ps 4000] [--T-melt 1400 --melt-ps 100] [--out file.json]
 
 Replicas are independent clusters of one batch (own initial velocities and
 bath seeds): they are melted together at T_melt, quenched to T, and stepped
@@ -227,9 +227,12 @@ def main(argv=None) -> int:
     ap.add_argument("--seed", type=int, default=820)
     ap.add_argument("--track", type=int, default=0, help="replicas whose D(t) and g(r) are recorded")
     ap.add_argument("--min-ps", type=float, default=0.0, help="run at least this long")
+    ap.add_argument("--T-melt", type=float, default=1400.0, help="bath temperature of the melt, K")
+    ap.add_argument("--melt-ps", type=float, default=100.0, help="length of the melt, ps")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
-    res = run(args.T, args.replicas, args.max_ps, seed=args.seed, track=args.track, min_ps=args.min_ps)
+    res = run(args.T, args.replicas, args.max_ps, T_melt=args.T_melt, melt_ps=args.melt_ps, seed=args.seed,
+              track=args.track, min_ps=args.min_ps)
     if args.out:
         with open(args.out, "w") as f:
             json.dump(res, f)

@@ -34,3 +34,30 @@ def test_candidate_shapes_are_supported_by_the_header():
     listed = set(re.findall(r"\((\d),(\d),(\d+)\)", hdr))
     for s in autotune.SHAPES:
         assert tuple(str(x) for x in s) in listed, s
+
+
+def test_candidates_follow_cluster_sizes():
+    small = autotune.candidate_plans([2243])
+    assert any(c["pairs"] == 3 for c, _ in small) and any(c["pairs"] == 1 for c, _ in small)
+    large = autotune.candidate_plans([48077])
+    assert all(c["pairs"] == 2 for c, _ in large)
+    assert any(16384 in t for c, t in large)
+    batch = autotune.candidate_plans(np.full(256, 1750))
+    assert not any(c["pairs"] == 3 for c, _ in batch)
+
+
+def test_committed_table_covers_the_benchmark_workloads():
+    import os
+    from paper_1210_3559_amd import inputs
+    assert os.path.exists(autotune.DEFAULT_CACHE)
+    table = autotune.load_cache()
+    for name in ("ni2243_cooling", "ni15000_fp64", "ni15000_mixed", "ni48077_allpairs", "batch256", "batch256_mixed"):
+        w = inputs.by_name(name)
+        t = autotune.lookup(w.offsets, w.precision)
+        assert t is not None, name
+        assert t["pairs"] in (1, 2, 3)
+        if t["pairs"] == 2:
+            assert t["ipt"] in (2, 4, 8)
+        if t["pairs"] == 1:
+            assert (t["ipt"], t["waves_i"], t["waves_j"]) in autotune.SHAPES
+    assert all("ms_per_step" in e and "workload" in e for e in table.values())
