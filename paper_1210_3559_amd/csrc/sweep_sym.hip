@@ -107,8 +107,8 @@ __device__ __forceinline__ void sym_force_pair(double dx, double dy, double dz, 
     if constexpr (EN) eu += un;
 }
 
-// EN: accumulate the pair energy (u^n); without it the energy partials are
-// written as zero (steps whose energies nobody reads).
+// EN: accumulate and store the pair energy (u^n); without it (steps whose
+// energies nobody reads) the energy partials are neither summed nor stored.
 template <int IPT, int PREC, bool EN>
 __global__ __launch_bounds__(64) void k_sym_force(const SymItem *__restrict__ items, const int32_t *__restrict__ order,
                                                   const SymTile *__restrict__ tiles, const double4 *__restrict__ xp,
@@ -211,17 +211,16 @@ __global__ __launch_bounds__(64) void k_sym_force(const SymItem *__restrict__ it
         for (int p = 0; p < IPT; ++p) eu[p] *= 2.0;  // each unordered pair once
     }
 #pragma unroll
-    for (int p = 0; p < IPT; ++p) {
-        unscale_force<PREC, false>(fx[p], fy[p], fz[p], eu[p]);
-        if constexpr (!EN) eu[p] = 0.0;
-    }
+    for (int p = 0; p < IPT; ++p) unscale_force<PREC, false>(fx[p], fy[p], fz[p], eu[p]);
     double *out = ipart + (size_t)it.slot * 4 * 64 * IPT;
 #pragma unroll
     for (int p = 0; p < IPT; ++p) {
         out[(0 * IPT + p) * 64 + lane] = fx[p];
         out[(1 * IPT + p) * 64 + lane] = fy[p];
         out[(2 * IPT + p) * 64 + lane] = fz[p];
-        out[(3 * IPT + p) * 64 + lane] = eu[p];
+        // steps without the pair energy leave its slot unwritten (the reduce
+        // of such a step does not read it)
+        if constexpr (EN) out[(3 * IPT + p) * 64 + lane] = eu[p];
     }
 }
 
@@ -316,42 +315,45 @@ __global__ __launch_bounds__(64) void k_sym_density(const SymItem *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Reduce + finish: one workgroup of 256 threads per 64-atom tile.  Thread
-// (g4, lane): g4 = 0..3 interleaves the j-side partials; i-side items are
-// summed by g4 == 0.  Group sums are combined in g4 order.
+// Reduce + finish: one workgroup of 512 threads per 64-atom tile.  Thread
+// (g8, lane), g8 = 0..7, adds the tile's i-side items k and j-side partials
+// g with k, g = g8 (mod 8) (items first, each run in increasing order); the
+// eight sums are combined in g8 order, so the result is deterministic.
+// Q = 1: density; Q = 4: force and pair energy (the energy only when the
+// sweep accumulated it, EN; otherwise it is zero and was not stored).
 // ---------------------------------------------------------------------------
-constexpr int kSymRed = 256;
+constexpr int kSymRed = 512;
+constexpr int kSymRedGroups = kSymRed / 64;
 
-template <int IPT, int Q>
+template <int IPT, int Q, bool EN>
 __device__ __forceinline__ void sym_sums(const SymTile &t, const double *__restrict__ ipart,
                                          const double *__restrict__ jpart, double *sh) {
-    const int lane = threadIdx.x & 63, g4 = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, g8 = threadIdx.x >> 6;
+    constexpr int QI = (Q == 4 && !EN) ? 3 : Q;  // i-side values read
+    constexpr int QJ = Q == 4 ? 3 : 1;           // the j side carries no energy
     double s[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) s[q] = 0.0;
     if (lane < t.ni) {
-        if (g4 == 0) {
-            for (int k = 0; k < t.nitems; ++k) {
-                const double *p = ipart + (size_t)(t.item0 + k) * Q * 64 * IPT + t.p * 64 + lane;
+        for (int k = g8; k < t.nitems; k += kSymRedGroups) {
+            const double *p = ipart + (size_t)(t.item0 + k) * Q * 64 * IPT + t.p * 64 + lane;
 #pragma unroll
-                for (int q = 0; q < Q; ++q) s[q] += p[(size_t)q * IPT * 64];
-            }
+            for (int q = 0; q < QI; ++q) s[q] += p[(size_t)q * IPT * 64];
         }
-        constexpr int QJ = Q == 4 ? 3 : 1;  // the j side carries no energy
-        for (int g = g4; g < t.nj; g += 4) {
+        for (int g = g8; g < t.nj; g += kSymRedGroups) {
             const double *p = jpart + ((size_t)(t.jbase + g) * QJ) * 64 + lane;
 #pragma unroll
             for (int q = 0; q < QJ; ++q) s[q] += p[q * 64];
         }
     }
 #pragma unroll
-    for (int q = 0; q < Q; ++q) sh[(g4 * Q + q) * 64 + lane] = s[q];
+    for (int q = 0; q < Q; ++q) sh[(g8 * Q + q) * 64 + lane] = s[q];
     __syncthreads();
-    if (g4 == 0) {
+    if (g8 == 0) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             double v = sh[q * 64 + lane];
-            for (int gg = 1; gg < 4; ++gg) v += sh[(gg * Q + q) * 64 + lane];
+            for (int gg = 1; gg < kSymRedGroups; ++gg) v += sh[(gg * Q + q) * 64 + lane];
             sh[q * 64 + lane] = v;
         }
     }
@@ -363,25 +365,25 @@ __global__ __launch_bounds__(kSymRed) void k_sym_density_reduce(const SymTile *_
                                                                 const double *__restrict__ ipart,
                                                                 const double *__restrict__ jpart, DensityOut o,
                                                                 PotConst pc) {
-    __shared__ double sh[4 * 64];
+    __shared__ double sh[kSymRedGroups * 64];
     __shared__ double sh_red[kSymRed];
     const SymTile t = tiles[blockIdx.x];
-    sym_sums<IPT, 1>(t, ipart, jpart, sh);
+    sym_sums<IPT, 1, false>(t, ipart, jpart, sh);
     double emb = 0.0;
     if (threadIdx.x < t.ni) emb = density_atom(t.i0 + threadIdx.x, sh[threadIdx.x], o, pc);
     emb = block_sum<kSymRed>(emb, sh_red);
     if (threadIdx.x == 0) o.tile_sums[(size_t)blockIdx.x * kTileSums + 0] = emb;
 }
 
-template <int IPT>
+template <int IPT, bool EN>
 __global__ __launch_bounds__(kSymRed) void k_sym_force_reduce(const SymTile *__restrict__ tiles,
                                                               const double *__restrict__ ipart,
                                                               const double *__restrict__ jpart, ForceOut o,
                                                               PotConst pc) {
-    __shared__ double sh[4 * 4 * 64];
+    __shared__ double sh[kSymRedGroups * 4 * 64];
     __shared__ double sh_red[kSymRed];
     const SymTile t = tiles[blockIdx.x];
-    sym_sums<IPT, 4>(t, ipart, jpart, sh);
+    sym_sums<IPT, 4, EN>(t, ipart, jpart, sh);
     double epair = 0.0, v2 = 0.0;
     const int l = threadIdx.x;
     if (l < t.ni) force_atom(t.i0 + l, sh[l], sh[64 + l], sh[128 + l], sh[192 + l], o, pc, epair, v2);
@@ -410,8 +412,12 @@ hipError_t launch_ipt(bool force, int stage, bool energy, const SymLaunch &L, co
     }
     if (stage == 1 && L.ntiles > 0) {
         if (force) {
-            hipLaunchKernelGGL((k_sym_force_reduce<IPT>), dim3(L.ntiles), dim3(kSymRed), 0, s, L.tiles, L.ipart,
-                               L.jpart, fo, pc);
+            if (energy)
+                hipLaunchKernelGGL((k_sym_force_reduce<IPT, true>), dim3(L.ntiles), dim3(kSymRed), 0, s, L.tiles,
+                                   L.ipart, L.jpart, fo, pc);
+            else
+                hipLaunchKernelGGL((k_sym_force_reduce<IPT, false>), dim3(L.ntiles), dim3(kSymRed), 0, s, L.tiles,
+                                   L.ipart, L.jpart, fo, pc);
         } else {
             const DensityOut o{B.rp, B.xp, B.rho, B.tile_sums};
             hipLaunchKernelGGL((k_sym_density_reduce<IPT>), dim3(L.ntiles), dim3(kSymRed), 0, s, L.tiles, L.ipart,
