@@ -211,6 +211,22 @@ int scmd_set_thermostat(scmd_ctx *ctx, int cluster, int kind, double T_start_K, 
 int scmd_set_langevin(scmd_ctx *ctx, int cluster, double T_start_K, double T_end_K, int64_t ramp_steps,
                       double gamma_per_ps, uint64_t seed);
 
+/* Margin of the cell list (neighbour SCMD_CELLLIST), A (default 0.4):
+ * cells of edge >= rc + skin, and per-atom lists of the candidates within
+ * rc + skin, are rebuilt only once an atom has moved more than skin / 2
+ * since the last rebuild, and reused in between (every pair closer than rc
+ * is then still listed; the pair terms apply rc themselves).  skin = 0
+ * rebuilds every step.  Results are the same up to summation order (the
+ * order of a list's entries).  SCMD_EINVAL for a negative or non-finite
+ * skin; takes effect at the next evaluation. */
+int scmd_set_cell_skin(scmd_ctx *ctx, double skin_A);
+
+/* Rebuilds of the cell list's cells and lists since it was planned (the
+ * first evaluation, a change of potential, integrator or skin, or new
+ * clusters plan it afresh); 0 without a cell list.  Synchronises the
+ * context stream. */
+int scmd_get_cell_rebuilds(scmd_ctx *ctx, int64_t *rebuilds);
+
 /* Override the sweep launch shape (NULL restores defaults). */
 int scmd_set_tuning(scmd_ctx *ctx, const scmd_tuning *tuning);
 
@@ -358,10 +374,13 @@ int scmd_diffusion(scmd_ctx *ctx, int cluster, int64_t first, int nframes, doubl
                    int segments, double *D_A2_per_ps, int64_t *n_central);
 
 /* Checkpoint: scmd_get_state writes a self-describing blob (positions,
- * velocities, forces, thermostat factors and settings, step counts) into buf
- * of *bytes capacity; with buf NULL it only stores the needed size in *bytes.
+ * velocities, forces, thermostat factors and settings, step counts, and for
+ * the cell list the positions of its last rebuild) into buf of *bytes
+ * capacity; with buf NULL it only stores the needed size in *bytes.
  * scmd_set_state restores a blob taken from a context with the same cluster
- * layout; stepping on from it reproduces the uninterrupted run bit for bit. */
+ * layout (for the cell list it also rebuilds the cells and lists from those
+ * positions, so the potential and integrator must be set for that); stepping
+ * on from it reproduces the uninterrupted run bit for bit. */
 int scmd_get_state(scmd_ctx *ctx, void *buf, size_t *bytes);
 int scmd_set_state(scmd_ctx *ctx, const void *buf, size_t bytes);
 

@@ -49,6 +49,12 @@ struct CellGrid {
 struct CellList {
     int nclusters = 0, natoms = 0, total_cap = 0, tile = 0, tile_shift = 0;
     double rc = 0.0;
+    double skin = 0.0;            // list margin: cells and lists cover rl = rc + skin
+    double rl = 0.0;
+    double4 *ref = nullptr;       // [natoms] positions at the last build (atom order)
+    int *slot_of = nullptr;       // [natoms] atom -> its slot in the cell order of the last build
+    int *flag = nullptr;          // [1] 1: the next force evaluation rebuilds the cells and lists
+    unsigned long long *nbuilds = nullptr;  // [1] rebuilds since the plan
     CellGrid *grid = nullptr;     // [nclusters] this step's grids
     CellGrid *grid0 = nullptr;    // [nclusters] fixed fields (capacity, base, atoms)
     int *cell_cluster = nullptr;  // [total_cap]
@@ -100,15 +106,29 @@ __device__ __forceinline__ double ord_decode(long long b) {
 // Partial bounding boxes: one workgroup per chunk of at most kBBoxChunk
 // atoms of one cluster; min/max are exact, so neither the reduction order
 // nor the atomic merge order matters.
+//
+// The same pass checks the lists of the last build: when an atom has moved
+// more than half the skin since then (|r - ref|^2 > thr2; thr2 < 0: every
+// step), two atoms may have come closer than rc without being listed, and
+// the flag asks for a rebuild.  It also copies the positions into the cell
+// order of the last build (rs), which the density sweep stages.
 __global__ __launch_bounds__(kBBoxBlock) void k_cell_bbox(const int4 *__restrict__ chunks,
                                                           const double4 *__restrict__ rp,
-                                                          long long *__restrict__ box) {
+                                                          long long *__restrict__ box,
+                                                          const double4 *__restrict__ ref, double thr2,
+                                                          const int *__restrict__ slot_of,
+                                                          double4 *__restrict__ rs, int *__restrict__ flag) {
     __shared__ double sh[6][kBBoxBlock / 64];
     const int4 ch = chunks[blockIdx.x];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double m[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    bool moved = false;
     for (int i = ch.y + threadIdx.x; i < ch.z; i += kBBoxBlock) {
         const double4 q = rp[i];
+        const double4 o = ref[i];
+        const double ex = q.x - o.x, ey = q.y - o.y, ez = q.z - o.z;
+        moved = moved || !(ex * ex + ey * ey + ez * ez <= thr2);
+        rs[slot_of[i]] = q;
         m[0] = fmin(m[0], q.x);
         m[1] = fmin(m[1], q.y);
         m[2] = fmin(m[2], q.z);
@@ -124,6 +144,7 @@ __global__ __launch_bounds__(kBBoxBlock) void k_cell_bbox(const int4 *__restrict
             m[3 + d] = fmax(m[3 + d], __shfl_xor(m[3 + d], o, 64));
         }
     }
+    if (__ballot(moved) != 0ull && lane == 0) atomicOr(flag, 1);
     if (lane == 0)
         for (int d = 0; d < 6; ++d) sh[d][w] = m[d];
     __syncthreads();
@@ -227,13 +248,20 @@ __device__ __forceinline__ int wave_cell_add(int *__restrict__ ctr, int cell, in
 
 // Per atom: the grid of its cluster from this step's bounding box (every
 // thread of a cluster computes the same grid; the cluster's first atom stores
-// it for the sweeps), its cell, and the per-cell counts.
+// it for the sweeps), its cell, and the per-cell counts.  Thread t takes the
+// atom at slot t of the previous build's cell order (prev), so the lanes of
+// a wavefront mostly fall into a few cells and share their atomics even
+// after the atoms have mixed (the atom order itself carries no locality in a
+// liquid).
 __global__ __launch_bounds__(256) void k_cell_count(const CellGrid *__restrict__ grid0, CellGrid *__restrict__ grid,
                                                     const long long *__restrict__ box, double rc,
                                                     const int *__restrict__ atom_cluster,
-                                                    const double4 *__restrict__ rp, int *__restrict__ cell_of,
-                                                    int *__restrict__ count, int natoms) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+                                                    const double4 *__restrict__ rp, const int *__restrict__ prev,
+                                                    int *__restrict__ cell_of, int *__restrict__ count, int natoms,
+                                                    const int *__restrict__ flag) {
+    if (*flag == 0) return;  // the lists of the last build still hold
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = t < natoms ? prev[t] : natoms;
     int cell = -1;
     if (i < natoms) {
         const int c = atom_cluster[i];
@@ -263,10 +291,17 @@ constexpr int kOrderBins = 256;
 // read and the bounding boxes reset, ready for the next build.
 __global__ __launch_bounds__(kScanBlock) void k_cell_scan(int *__restrict__ count, int *__restrict__ start,
                                                           int *__restrict__ cursor, int *__restrict__ corder,
-                                                          int total, long long *__restrict__ box, int nclusters) {
+                                                          int total, long long *__restrict__ box, int nclusters,
+                                                          const int *__restrict__ flag,
+                                                          unsigned long long *__restrict__ nbuilds) {
     __shared__ int wsum[kScanBlock / 64];
     __shared__ int bins[kOrderBins];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (*flag == 0) {  // no build: only reset the boxes for the next check
+        for (int k = t; k < 6 * nclusters; k += kScanBlock) box[k] = ord_encode((k % 6) < 3 ? INFINITY : -INFINITY);
+        return;
+    }
+    if (t == 0) *nbuilds += 1ull;
     for (int q = t; q < kOrderBins; q += kScanBlock) bins[q] = 0;
     const int per = (total + kScanBlock - 1) / kScanBlock;
     const int a = min(total, t * per), b = min(total, a + per);
@@ -343,9 +378,14 @@ __global__ __launch_bounds__(kScanBlock) void k_cell_scan(int *__restrict__ coun
     for (int k = t; k < 6 * nclusters; k += kScanBlock) box[k] = ord_encode((k % 6) < 3 ? INFINITY : -INFINITY);
 }
 
-__global__ __launch_bounds__(256) void k_cell_scatter(const int *__restrict__ cell_of, int *__restrict__ cursor,
-                                                      int *__restrict__ perm, int natoms) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Per atom, in the previous build's cell order as for the counts: a slot in
+// its cell (which slot depends on timing; k_cell_order ranks them).
+__global__ __launch_bounds__(256) void k_cell_scatter(const int *__restrict__ cell_of, const int *__restrict__ prev,
+                                                      int *__restrict__ cursor, int *__restrict__ perm, int natoms,
+                                                      const int *__restrict__ flag) {
+    if (*flag == 0) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = t < natoms ? prev[t] : natoms;
     const int cell = i < natoms ? cell_of[i] : -1;
     const int slot = wave_cell_add<true>(cursor, cell, threadIdx.x & 63);
     if (i < natoms) perm[slot] = i;
@@ -361,8 +401,10 @@ constexpr int kOrderLds = 1024;
 
 __global__ __launch_bounds__(64) void k_cell_order(const int *__restrict__ start, const int *__restrict__ perm,
                                                    int *__restrict__ sperm, const double4 *__restrict__ rp,
-                                                   double4 *__restrict__ rs) {
+                                                   double4 *__restrict__ rs, double4 *__restrict__ ref,
+                                                   int *__restrict__ slot_of, const int *__restrict__ flag) {
     __shared__ int sh[kOrderLds];
+    if (*flag == 0) return;
     const int a = start[blockIdx.x], n = start[blockIdx.x + 1] - a;
     if (n == 0) return;
     const bool local = n <= kOrderLds;
@@ -376,7 +418,10 @@ __global__ __launch_bounds__(64) void k_cell_order(const int *__restrict__ start
         int rank = 0;
         for (int q = 0; q < n; ++q) rank += src[q] < v ? 1 : 0;
         sperm[a + rank] = v;
-        rs[a + rank] = rp[v];
+        slot_of[v] = a + rank;
+        const double4 q = rp[v];
+        rs[a + rank] = q;
+        ref[v] = q;
     }
 }
 
@@ -397,7 +442,7 @@ __global__ __launch_bounds__(64) void k_cell_order(const int *__restrict__ start
 // than the LDS buffer (only when cells coarsened after an atom escaped) read
 // every candidate from global memory and mask the pairs beyond rc.
 constexpr int kCellWaves = 16;
-constexpr int kCellStage = 2048;  // staged candidates (64 KiB: two workgroups per CU)
+constexpr int kCellStage = 2240;  // staged candidates (70 KiB + the queues: two workgroups per CU)
 constexpr int kCellQueue = 128;   // in-range candidates queued per wavefront (< 64 left + 64 new)
 constexpr int kCellNbrCap = 512;  // listed candidates within rc per atom (an atom with more re-tests)
 
@@ -412,7 +457,8 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
                                                                 double *__restrict__ part, int tile_shift,
                                                                 uint16_t *__restrict__ nbr,
                                                                 int *__restrict__ nbr_n,
-                                                                const double4 *__restrict__ xp, PotConst pc) {
+                                                                const double4 *__restrict__ xp, PotConst pc,
+                                                                int *__restrict__ flag, double rl2) {
     constexpr int Q = FORCE ? 4 : 1;
     // staged candidates as four arrays (x, y, z, w): lanes reading
     // consecutive candidates touch consecutive 8-byte words, conflict-free
@@ -421,6 +467,12 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
                   *const lw = lds_c + 3 * kCellStage;
     __shared__ int seg_lo[9], seg_len[9], seg_off[10];
     __shared__ int queue[kCellWaves][kCellQueue];
+    // A density sweep after a (re)build lists every atom's candidates within
+    // rl = rc + skin while it runs; until the next build both sweeps read
+    // those lists.  The force sweep ends the build (no later kernel of this
+    // evaluation reads the flag).
+    const bool build = !FORCE && *flag != 0;
+    if (FORCE && blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
     const int cell = corder[blockIdx.x];
     const CellGrid g = grid[cell_cluster[cell]];
     const int local = cell - g.base;
@@ -499,11 +551,12 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
                 density_pair<PREC, GEN, true, true>(qi.x - q.x, qi.y - q.y, qi.z - q.z, off, acc[0], pc);
         };
         uint16_t *const list = nbr + (size_t)k * kCellNbrCap;
-        const int listed = FORCE && staged ? __builtin_amdgcn_readfirstlane(nbr_n[k]) : -1;
-        if (FORCE && staged && listed <= kCellNbrCap) {
-            // the density sweep of this step listed the candidates within rc
-            // (same cell list, same positions); lanes take the entries in the
-            // order the queue below hands them out
+        const int listed = !build && staged ? __builtin_amdgcn_readfirstlane(nbr_n[k]) : -1;
+        if (!build && staged && listed <= kCellNbrCap) {
+            // the density sweep of the last build listed the candidates
+            // within rl (same cells; no atom has moved half the skin since,
+            // so every pair now closer than rc is among them); lanes take the
+            // entries in the order the queue below handed them out
             for (int base = 0; base < listed; base += 64) {
                 const bool v = base + lane < listed;
                 const int e = list[v ? base + lane : base];  // in bounds for every lane
@@ -511,19 +564,22 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
             }
         } else if (staged) {
             // Only about a fifth of the candidates lie within rc.  A first pass
-            // tests r^2 < rc^2 and queues the hits (ring buffer per
+            // tests r^2 < rt^2 and queues the hits (ring buffer per
             // wavefront); every 64 queued hits make one pass of the pair
-            // terms with all lanes busy.  The test is the pair terms' own
-            // cutoff expression, so no pair changes side.  The density sweep
-            // also stores the hits as they leave the queue (up to kCellNbrCap
-            // per atom, one coalesced store per 64) for the force sweep.
+            // terms with all lanes busy.  The pair terms apply the cutoff
+            // themselves.  On a build the test radius is rl and the density
+            // sweep stores the hits as they leave the queue (up to kCellNbrCap
+            // per atom, one coalesced store per 64) for the sweeps until the
+            // next build; otherwise (an atom whose list overflowed) it is rc
+            // with the pair terms' own expression, so no pair changes side.
+            const double rt2 = build ? rl2 : pc.rc2;
             int *qu = queue[wave];
             int head = 0, qn = 0, total = 0;  // wavefront-uniform
             for (int base = 0; base < M64; base += 64) {
                 const int p = base + lane;
                 const double dx = qi.x - lx[p], dy = qi.y - ly[p], dz = qi.z - lz[p];
                 const bool in =
-                    (__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)) < pc.rc2) & (lane != self_p - base);
+                    (__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)) < rt2) & (lane != self_p - base);
                 const unsigned long long hit = __ballot(in);
                 const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(hit >> 32),
                                                            __builtin_amdgcn_mbcnt_lo((unsigned)hit, 0u));
@@ -534,7 +590,7 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
                     const int e = qu[(head + lane) & (kCellQueue - 1)];
                     head = (head + 64) & (kCellQueue - 1);
                     qn -= 64;
-                    if (!FORCE && total + 64 <= kCellNbrCap) list[total + lane] = (uint16_t)e;
+                    if (build && total + 64 <= kCellNbrCap) list[total + lane] = (uint16_t)e;
                     total += 64;
                     pair_terms(staged_cand(e), false);
                 }
@@ -545,11 +601,11 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
                 // lanes past the queue read candidate 0 (valid: the own cell
                 // is not empty) and add nothing
                 const int e = v ? qu[(head + lane) & (kCellQueue - 1)] : 0;
-                if (!FORCE && v && total + lane < kCellNbrCap) list[total + lane] = (uint16_t)e;
+                if (build && v && total + lane < kCellNbrCap) list[total + lane] = (uint16_t)e;
                 total += qn;
                 pair_terms(staged_cand(e), !v);
             }
-            if (!FORCE && lane == 0) nbr_n[k] = total;
+            if (build && lane == 0) nbr_n[k] = total;
         } else {
 #pragma unroll 2
             for (int p = lane; p < M; p += 64) pair_terms(staged ? staged_cand(p) : rec(cand(p)), p == self_p);
@@ -581,7 +637,7 @@ hipError_t launch_cell_sweep(CellList *cl, double *part, const double4 *xp, cons
     const size_t lds = kCellStage * sizeof(double4);
 #define SCMD_CELL_ARGS                                                                                          \
     cl->grid, cl->corder, cl->cell_cluster, cl->start, cl->rs, cl->sperm, cl->pslot, part, cl->tile_shift, cl->nbr, \
-        cl->nbr_n, xp, pc
+        cl->nbr_n, xp, pc, cl->flag, cl->rl * cl->rl
     if (precision == SCMD_FP64) {
         if (pc.generic)
             hipLaunchKernelGGL((k_cell_sweep<SCMD_FP64, true, FORCE>), grid, block, lds, s, SCMD_CELL_ARGS);
@@ -611,20 +667,44 @@ CellList *cell_list_create() {
 
 void cell_list_destroy(CellList *cl) {
     if (!cl) return;
-    void *ptrs[] = {cl->grid0, cl->grid,  cl->cell_cluster, cl->count,        cl->start, cl->cursor, cl->cell_of,
-                    cl->perm,  cl->sperm, cl->box,          cl->chunks,       cl->pslot, cl->atom_cluster,
-                    cl->rs,    cl->nbr,   cl->nbr_n,        cl->corder};
+    void *ptrs[] = {cl->grid0, cl->grid,  cl->cell_cluster, cl->count,  cl->start, cl->cursor,
+                    cl->cell_of, cl->perm, cl->sperm, cl->box, cl->chunks, cl->pslot,
+                    cl->atom_cluster, cl->rs, cl->nbr, cl->nbr_n, cl->corder, cl->ref,
+                    cl->slot_of, cl->flag, cl->nbuilds};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete cl;
 }
 
-hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, double rc, const double4 *rp_dev,
-                          const ITile *tiles, int ntiles, int tile) {
+// The sweeps stage more than the default 64 KiB of dynamic LDS: raise each
+// instantiation's limit (once per plan, outside any graph capture).
+static hipError_t set_cell_sweep_lds() {
+    const int lds = (int)(kCellStage * sizeof(double4));
+    const void *fns[] = {reinterpret_cast<const void *>(k_cell_sweep<SCMD_FP64, false, false>),
+                         reinterpret_cast<const void *>(k_cell_sweep<SCMD_FP64, false, true>),
+                         reinterpret_cast<const void *>(k_cell_sweep<SCMD_FP64, true, false>),
+                         reinterpret_cast<const void *>(k_cell_sweep<SCMD_FP64, true, true>),
+                         reinterpret_cast<const void *>(k_cell_sweep<SCMD_MIXED, false, false>),
+                         reinterpret_cast<const void *>(k_cell_sweep<SCMD_MIXED, false, true>),
+                         reinterpret_cast<const void *>(k_cell_sweep<SCMD_MIXED, true, false>),
+                         reinterpret_cast<const void *>(k_cell_sweep<SCMD_MIXED, true, true>)};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, double rc, double skin,
+                          const double4 *rp_dev, const ITile *tiles, int ntiles, int tile) {
+    if (hipError_t e0 = set_cell_sweep_lds(); e0 != hipSuccess) return e0;
     const int natoms = (int)offsets[nclusters];
     cl->nclusters = nclusters;
     cl->natoms = natoms;
     cl->rc = rc;
+    cl->skin = skin;
+    cl->rl = rc + skin;
+    rc = cl->rl;  // cells cover the list radius
     cl->tile = tile;
     cl->tile_shift = 0;
     while ((1 << cl->tile_shift) < tile) ++cl->tile_shift;
@@ -704,6 +784,16 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
     if ((e = dalloc(&cl->rs, natoms)) != hipSuccess) return e;
     if ((e = dalloc(&cl->nbr, (size_t)natoms * kCellNbrCap)) != hipSuccess) return e;
     if ((e = dalloc(&cl->nbr_n, natoms)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->ref, natoms)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->slot_of, natoms)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->flag, 1)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->nbuilds, 1)) != hipSuccess) return e;
+    if ((e = hipMemset(cl->nbuilds, 0, sizeof(unsigned long long))) != hipSuccess) return e;
+    {
+        const int one = 1;  // the first evaluation builds
+        if ((e = hipMemcpy(cl->flag, &one, sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) return e;
+    }
+    if (natoms > 0 && (e = hipMemset(cl->ref, 0, natoms * sizeof(double4))) != hipSuccess) return e;
     if ((e = hipMemcpy(cl->grid, grids.data(), nclusters * sizeof(CellGrid), hipMemcpyHostToDevice)) != hipSuccess)
         return e;
     if ((e = hipMemcpy(cl->grid0, grids.data(), nclusters * sizeof(CellGrid), hipMemcpyHostToDevice)) != hipSuccess)
@@ -712,6 +802,13 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
         (e = hipMemcpy(cl->cell_cluster, cell_cluster.data(), base * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
         return e;
     if (natoms > 0) {
+        // before the first build the "previous cell order" is the atom order
+        std::vector<int> ident(natoms);
+        for (int i = 0; i < natoms; ++i) ident[i] = i;
+        if ((e = hipMemcpy(cl->sperm, ident.data(), natoms * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+            return e;
+        if ((e = hipMemcpy(cl->slot_of, ident.data(), natoms * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+            return e;
         if ((e = hipMemcpy(cl->pslot, pslot.data(), natoms * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
             return e;
         if ((e = hipMemcpy(cl->atom_cluster, ac.data(), natoms * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
@@ -723,18 +820,61 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
 hipError_t cell_list_build(CellList *cl, const double4 *rp, hipStream_t s) {
     (void)hipGetLastError();
     const int na = cl->natoms, tc = cl->total_cap;
+    // rebuild once an atom has moved half the skin (every step without one)
+    const double half = 0.5 * cl->skin;
+    const double thr2 = cl->skin > 0.0 ? half * half : -1.0;
     if (cl->nchunks > 0)
-        hipLaunchKernelGGL(k_cell_bbox, dim3(cl->nchunks), dim3(kBBoxBlock), 0, s, cl->chunks, rp, cl->box);
+        hipLaunchKernelGGL(k_cell_bbox, dim3(cl->nchunks), dim3(kBBoxBlock), 0, s, cl->chunks, rp, cl->box, cl->ref,
+                           thr2, cl->slot_of, cl->rs, cl->flag);
     if (na > 0)
-        hipLaunchKernelGGL(k_cell_count, dim3((na + 255) / 256), dim3(256), 0, s, cl->grid0, cl->grid, cl->box, cl->rc,
-                           cl->atom_cluster, rp, cl->cell_of, cl->count, na);
+        hipLaunchKernelGGL(k_cell_count, dim3((na + 255) / 256), dim3(256), 0, s, cl->grid0, cl->grid, cl->box, cl->rl,
+                           cl->atom_cluster, rp, cl->sperm, cl->cell_of, cl->count, na, cl->flag);
     hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(kScanBlock), 0, s, cl->count, cl->start, cl->cursor, cl->corder, tc,
-                       cl->box, cl->nclusters);
+                       cl->box, cl->nclusters, cl->flag, cl->nbuilds);
     if (na > 0)
-        hipLaunchKernelGGL(k_cell_scatter, dim3((na + 255) / 256), dim3(256), 0, s, cl->cell_of, cl->cursor, cl->perm,
-                           na);
-    hipLaunchKernelGGL(k_cell_order, dim3(tc), dim3(64), 0, s, cl->start, cl->perm, cl->sperm, rp, cl->rs);
+        hipLaunchKernelGGL(k_cell_scatter, dim3((na + 255) / 256), dim3(256), 0, s, cl->cell_of, cl->sperm, cl->cursor,
+                           cl->perm, na, cl->flag);
+    // count and scatter read the previous build's order from sperm before
+    // k_cell_order replaces it
+    hipLaunchKernelGGL(k_cell_order, dim3(tc), dim3(64), 0, s, cl->start, cl->perm, cl->sperm, rp, cl->rs, cl->ref,
+                       cl->slot_of, cl->flag);
     return hipGetLastError();
+}
+
+// flag values copied to the device (static: an asynchronous copy may read
+// them after the call returns)
+static const int kFlagSet = 1, kFlagClear = 0;
+
+hipError_t cell_list_invalidate(CellList *cl, hipStream_t s) {
+    return hipMemcpyAsync(cl->flag, &kFlagSet, sizeof(int), hipMemcpyHostToDevice, s);
+}
+
+hipError_t cell_list_rebuilds(CellList *cl, int64_t *out) {
+    unsigned long long n = 0;
+    hipError_t e = hipMemcpy(&n, cl->nbuilds, sizeof(n), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) *out = (int64_t)n;
+    return e;
+}
+
+hipError_t cell_list_get_ref(CellList *cl, double4 *host_out) {
+    if (cl->natoms == 0) return hipSuccess;
+    return hipMemcpy(host_out, cl->ref, cl->natoms * sizeof(double4), hipMemcpyDeviceToHost);
+}
+
+hipError_t cell_list_restore(CellList *cl, const double4 *ref_host, double4 *scratch_dev, const SweepBuffers &B,
+                             const PotConst &pc, int precision, hipStream_t s) {
+    if (cl->natoms == 0) return cell_list_invalidate(cl, s);
+    hipError_t e = hipMemcpyAsync(scratch_dev, ref_host, cl->natoms * sizeof(double4), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    // cells and lists of the positions of the last build, as that build made
+    // them: a build forced from those positions, then a density sweep that
+    // lists the candidates (its sums are scratch, overwritten by the next
+    // evaluation)
+    if ((e = cell_list_invalidate(cl, s)) != hipSuccess) return e;
+    if ((e = cell_list_build(cl, scratch_dev, s)) != hipSuccess) return e;
+    if ((e = launch_cell_sweep<false>(cl, B.part, nullptr, pc, precision, s)) != hipSuccess) return e;
+    // the density sweep left the flag set: clear it (the lists hold)
+    return hipMemcpyAsync(cl->flag, &kFlagClear, sizeof(int), hipMemcpyHostToDevice, s);
 }
 
 hipError_t cell_list_density(CellList *cl, const SweepBuffers &B, const ITile *tiles, int ntiles, int tile,

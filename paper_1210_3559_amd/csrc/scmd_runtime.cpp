@@ -160,6 +160,8 @@ struct scmd_ctx {
 
     // cell-list plan (cutoff variant)
     CellList *cells = nullptr;
+    double cell_skin = 0.4;          // list margin of the cell list, A
+    DevBuf<double4> restore_scratch;  // checkpoint restore of the cell lists
 
     // progress
     bool have_forces = false;
@@ -663,7 +665,7 @@ int ensure_plan(scmd_ctx *c) {
     if (c->neighbour == SCMD_CELLLIST) {
         if (!c->cells) c->cells = cell_list_create();
         if (!c->cells) return fail(c, SCMD_ENOMEM, "cell list allocation failed");
-        hipError_t e = cell_list_plan(c->cells, c->nclusters, c->offsets.data(), c->params.rc, c->rp.p,
+        hipError_t e = cell_list_plan(c->cells, c->nclusters, c->offsets.data(), c->params.rc, c->cell_skin, c->rp.p,
                                       tiles.data(), c->ntiles, c->tile);
         if (e == hipSuccess) e = hipMemset(c->d_part.p, 0, c->d_part.n * sizeof(double));
         if (e != hipSuccess) return fail(c, SCMD_EDEVICE, std::string("cell list plan: ") + hipGetErrorString(e));
@@ -987,6 +989,7 @@ void release_device(scmd_ctx *c) {
     c->d_stiles.release();
     c->d_ipart.release();
     c->d_jpart.release();
+    c->restore_scratch.release();
     for (auto &fs : c->frames) fs.buf.release();
     c->frames.clear();
     c->diff_seg.release();
@@ -1007,8 +1010,10 @@ struct StateHeader {
     int32_t pad;
 };
 
+// offsets, r, v, F (double4), rho, cluster tables, and the positions of the
+// cell list's last build (double4; zero without a cell list)
 size_t state_bytes(const scmd_ctx *c) {
-    return sizeof(StateHeader) + (c->nclusters + 1) * sizeof(int64_t) + 3 * (size_t)c->natoms * sizeof(double4) +
+    return sizeof(StateHeader) + (c->nclusters + 1) * sizeof(int64_t) + 4 * (size_t)c->natoms * sizeof(double4) +
            (size_t)c->natoms * sizeof(double) + (size_t)c->nclusters * (sizeof(ClusterDesc) + sizeof(ClusterState));
 }
 
@@ -1313,6 +1318,35 @@ int scmd_set_langevin(scmd_ctx *ctx, int cluster, double T_start_K, double T_end
         d.ramp_origin = ctx->step;
     }
     return apply_thermostat_change(ctx);
+}
+
+int scmd_set_cell_skin(scmd_ctx *ctx, double skin_A) {
+    if (!ctx) return SCMD_EINVAL;
+    if (!(skin_A >= 0.0) || !std::isfinite(skin_A)) return fail(ctx, SCMD_EINVAL, "skin must be finite and >= 0");
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        ctx->cell_skin = skin_A;
+        if (ctx->neighbour == SCMD_CELLLIST) {
+            ctx->plan_ok = false;  // new cells and lists at the next evaluation
+            drop_graph(ctx);
+        }
+        return SCMD_OK;
+    })
+}
+
+int scmd_get_cell_rebuilds(scmd_ctx *ctx, int64_t *rebuilds) {
+    if (!ctx || !rebuilds) return SCMD_EINVAL;
+    if (ctx->neighbour != SCMD_CELLLIST || !ctx->cells || !ctx->plan_ok) {
+        *rebuilds = 0;
+        return SCMD_OK;
+    }
+    SCMD_GUARD({
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        HIP_TRY(ctx, cell_list_rebuilds(ctx->cells, rebuilds));
+        return SCMD_OK;
+    })
 }
 
 int scmd_set_tuning(scmd_ctx *ctx, const scmd_tuning *t) {
@@ -1712,7 +1746,7 @@ int scmd_get_state(scmd_ctx *ctx, void *buf, size_t *bytes) {
         char *p = (char *)buf;
         StateHeader h{};
         std::memcpy(h.magic, "SCMDSTA1", 8);
-        h.version = 2;
+        h.version = 3;
         h.nclusters = ctx->nclusters;
         h.natoms = ctx->natoms;
         h.step = ctx->step;
@@ -1732,6 +1766,10 @@ int scmd_get_state(scmd_ctx *ctx, void *buf, size_t *bytes) {
         std::memcpy(p, ctx->cdesc.data(), ctx->nclusters * sizeof(ClusterDesc));
         p += ctx->nclusters * sizeof(ClusterDesc);
         HIP_TRY(ctx, hipMemcpy(p, ctx->d_state.p, ctx->nclusters * sizeof(ClusterState), hipMemcpyDeviceToHost));
+        p += ctx->nclusters * sizeof(ClusterState);
+        std::memset(p, 0, (size_t)ctx->natoms * sizeof(double4));
+        if (ctx->cells && ctx->plan_ok && ctx->neighbour == SCMD_CELLLIST)
+            HIP_TRY(ctx, cell_list_get_ref(ctx->cells, (double4 *)p));
         *bytes = need;
         return SCMD_OK;
     })
@@ -1743,7 +1781,7 @@ int scmd_set_state(scmd_ctx *ctx, const void *buf, size_t bytes) {
     if (bytes < sizeof(StateHeader)) return fail(ctx, SCMD_EINVAL, "blob too small");
     StateHeader h;
     std::memcpy(&h, buf, sizeof(h));
-    if (std::memcmp(h.magic, "SCMDSTA1", 8) != 0 || h.version != 2) return fail(ctx, SCMD_EINVAL, "not a state blob");
+    if (std::memcmp(h.magic, "SCMDSTA1", 8) != 0 || h.version != 3) return fail(ctx, SCMD_EINVAL, "not a state blob");
     if (h.nclusters != ctx->nclusters || h.natoms != ctx->natoms || bytes != state_bytes(ctx))
         return fail(ctx, SCMD_EINVAL, "blob has a different cluster layout");
     const char *p = (const char *)buf + sizeof(h);
@@ -1775,8 +1813,25 @@ int scmd_set_state(scmd_ctx *ctx, const void *buf, size_t bytes) {
         }
         p += ctx->nclusters * sizeof(ClusterDesc);
         HIP_TRY(ctx, hipMemcpy(ctx->d_state.p, p, ctx->nclusters * sizeof(ClusterState), hipMemcpyHostToDevice));
+        p += ctx->nclusters * sizeof(ClusterState);
         if (ctx->plan_ok) HIP_TRY(ctx, upload_cdesc(ctx));
         drop_graph(ctx);
+        if (ready(ctx) && ctx->neighbour == SCMD_CELLLIST) {
+            // the cells and lists of the checkpointed run's last build, so
+            // that stepping on repeats that run bit for bit
+            int rc = ensure_plan(ctx);
+            if (rc != SCMD_OK) return rc;
+            bool have_ref = false;  // a blob of a context without a cell list holds zeros here
+            for (size_t k = 0; k < 4 * (size_t)ctx->natoms && !have_ref; ++k) have_ref = ((const double *)p)[k] != 0.0;
+            if (have_ref) {
+                HIP_TRY(ctx, ctx->restore_scratch.ensure(std::max(ctx->natoms, 1)));
+                HIP_TRY(ctx, cell_list_restore(ctx->cells, (const double4 *)p, ctx->restore_scratch.p, buffers(ctx),
+                                               ctx->pc, ctx->precision, ctx->stream));
+            } else {
+                HIP_TRY(ctx, cell_list_invalidate(ctx->cells, ctx->stream));
+            }
+            HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        }
         ctx->step = h.step;
         ctx->have_forces = h.have_forces != 0;
         HIP_TRY(ctx, hipMemset(ctx->d_flag.p, 0, sizeof(int)));

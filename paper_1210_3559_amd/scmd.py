@@ -42,6 +42,7 @@ SCMD_KERNEL_FORCE = 1
 EXPORTS = (
     "scmd_abi_version", "scmd_status_string", "scmd_create", "scmd_destroy", "scmd_init_clusters",
     "scmd_set_potential", "scmd_set_integrator", "scmd_set_thermostat", "scmd_set_langevin", "scmd_set_tuning",
+    "scmd_set_cell_skin", "scmd_get_cell_rebuilds",
     "scmd_compute",
     "scmd_step", "scmd_step_async", "scmd_synchronize", "scmd_get_step", "scmd_get_energy",
     "scmd_get_temperature", "scmd_get_positions", "scmd_get_velocities", "scmd_get_forces", "scmd_get_density",
@@ -98,6 +99,8 @@ def load(path: str = LIB_PATH):
         "scmd_set_thermostat": (i32, [vp, i32, i32, dbl, dbl, i64, dbl]),
         "scmd_set_langevin": (i32, [vp, i32, dbl, dbl, i64, dbl, ctypes.c_uint64]),
         "scmd_set_tuning": (i32, [vp, ctypes.POINTER(_Tuning)]),
+        "scmd_set_cell_skin": (i32, [vp, dbl]),
+        "scmd_get_cell_rebuilds": (i32, [vp, ctypes.POINTER(i64)]),
         "scmd_compute": (i32, [vp]),
         "scmd_step": (i32, [vp, i64]),
         "scmd_step_async": (i32, [vp, i64]),
@@ -210,6 +213,16 @@ def scmd_set_tuning(ctx, ipt: int = 0, waves_i: int = 0, waves_j: int = 0, targe
                     pairs: int = 0) -> None:
     t = _Tuning(int(ipt), int(waves_i), int(waves_j), int(target_items), int(pairs))
     _check(ctx, load().scmd_set_tuning(ctx, ctypes.byref(t)))
+
+
+def scmd_set_cell_skin(ctx, skin_A: float) -> None:
+    _check(ctx, load().scmd_set_cell_skin(ctx, float(skin_A)))
+
+
+def scmd_get_cell_rebuilds(ctx) -> int:
+    n = ctypes.c_int64()
+    _check(ctx, load().scmd_get_cell_rebuilds(ctx, ctypes.byref(n)))
+    return n.value
 
 
 def scmd_compute(ctx) -> None:
@@ -466,6 +479,12 @@ class Simulation:
         else:
             scmd_set_thermostat(self.ctx, cluster, SCMD_BERENDSEN, th["T_start"], th["T_end"],
                                 th.get("ramp_steps", 0), th["tau"])
+
+    def set_cell_skin(self, skin_A: float):
+        scmd_set_cell_skin(self.ctx, skin_A)
+
+    def cell_rebuilds(self) -> int:
+        return scmd_get_cell_rebuilds(self.ctx)
 
     def set_sampling(self, every: int, capacity: int = 1024):
         scmd_set_sampling(self.ctx, every, capacity)

@@ -477,6 +477,77 @@ def test_cell_list_full_size_48k_sampled():
     assert ens[0][0] == pytest.approx(oracle.energy(w.pos, params=dict(rc=RC), nthreads=NT), rel=1e-10)
 
 
+def test_cell_list_skin_lists_follow_the_oracle():
+    # 2000 K liquid start, 150 steps of 2 fs with the default skin (0.4 A):
+    # cells and lists are reused between rebuilds and rebuilt once an atom
+    # has moved 0.2 A; the trajectory is the cutoff oracle's
+    w = inputs.c2_cooling()
+    th = dict(T_start=2000.0, T_end=2000.0, ramp_steps=0, tau=100.0)
+    print("[traj] Ni2243 cell list with skin lists, 150 steps", flush=True)
+    r_ref, v_ref, _, log = oracle.vv_run(w.pos, w.vel, 150, dt=2.0, thermostat=th, params=dict(rc=RC), nthreads=NT)
+    with scmd.Simulation(w.offsets, w.pos, w.vel, dt=2.0, rc=RC, thermostats=[th]) as sim:
+        sim.step(150)
+        nb = sim.cell_rebuilds()
+        r, v = sim.positions(), sim.velocities()
+        ep, ek, _ = sim.energy(0)
+    print(f"[traj] {nb} rebuilds in 151 force evaluations", flush=True)
+    assert 2 <= nb < 100
+    assert np.abs(r - r_ref).max() < 1e-9
+    assert np.abs(v - v_ref).max() < 1e-10
+    assert ep == pytest.approx(log[-1, 0], rel=1e-10)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cell_list_skin_matches_rebuild_every_step(precision):
+    # the same run with lists reused (skin 0.4 A) and rebuilt every step
+    # (skin 0): equal up to the order of each atom's sums
+    w = inputs.c2_cooling()
+    outs = []
+    for skin in (0.4, 0.0):
+        with scmd.Simulation(w.offsets, w.pos, w.vel, dt=2.0, rc=RC, precision=precision) as sim:
+            sim.set_cell_skin(skin)
+            sim.step(60)
+            outs.append((sim.positions(), sim.forces(), sim.cell_rebuilds()))
+    assert outs[1][2] == 61  # every force evaluation
+    assert outs[0][2] < 40
+    assert np.abs(outs[0][0] - outs[1][0]).max() < 1e-10
+    assert_forces_close(outs[0][1], outs[1][1], 1e-9 if precision == "fp64" else 1e-6)
+    # and the forces at the final positions are the oracle's
+    f_ref, _, _ = oracle.forces(outs[0][0], params=dict(rc=RC), nthreads=NT)
+    assert_forces_close(outs[0][1], f_ref, TOL[precision])
+
+
+def test_cell_list_checkpoint_resume_is_bitwise():
+    # the checkpoint carries the positions of the last rebuild, and restoring
+    # it rebuilds those cells and lists: the resumed run repeats the
+    # uninterrupted one bit for bit
+    w = inputs.c2_cooling()
+    with scmd.Simulation(w.offsets, w.pos, w.vel, dt=2.0, rc=RC, thermostats=w.thermostat) as sim:
+        sim.step(37)
+        blob = scmd.scmd_get_state(sim.ctx)
+        sim.step(53)
+        ra, va, ea = sim.positions(), sim.velocities(), sim.energy()
+    with scmd.Simulation(w.offsets, w.pos, w.vel, dt=2.0, rc=RC, thermostats=w.thermostat) as sim:
+        sim.step(5)  # cells and lists of another state, replaced by the checkpoint's
+        scmd.scmd_set_state(sim.ctx, blob)
+        sim.step(53)
+        np.testing.assert_array_equal(sim.positions(), ra)
+        np.testing.assert_array_equal(sim.velocities(), va)
+        assert sim.energy() == ea
+
+
+def test_cell_skin_argument_errors():
+    w = inputs.c2_cooling()
+    with scmd.Simulation(w.offsets, w.pos, w.vel, dt=2.0, rc=RC) as sim:
+        for bad in (-0.1, float("nan"), float("inf")):
+            with pytest.raises(scmd.ScmdError) as e:
+                sim.set_cell_skin(bad)
+            assert e.value.status == scmd.SCMD_EINVAL
+    with scmd.Simulation(w.offsets, w.pos, w.vel, dt=2.0) as sim:  # all pairs: no cell list
+        sim.step(3)
+        assert sim.cell_rebuilds() == 0
+
+
 def test_cell_list_is_deterministic():
     w = inputs.c2_cooling()
     outs = []
