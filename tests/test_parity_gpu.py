@@ -179,13 +179,13 @@ def _mixed_errors(sim, n, idx):
 def test_c4_mixed_error_along_the_run():
     # the precision form at 15,000 atoms, 1500 K NVE: force and energy error
     # against the FP64 oracle (evaluated at the GPU's positions) at steps 0,
-    # 1000 and 10000
+    # 1000, 10000 and 20000 (the whole run of the precision workload)
     w = inputs.c4_mixed()
     idx = np.random.default_rng(4).choice(w.n_atoms, 64, replace=False)
     with scmd.Simulation.from_workload(w, precision="mixed") as sim:
         sim.compute()
         errs = {0: _mixed_errors(sim, w.n_atoms, idx)}
-        for k, n in ((1000, 1000), (10000, 9000)):
+        for k, n in ((1000, 1000), (10000, 9000), (20000, 10000)):
             sim.step(n)
             errs[k] = _mixed_errors(sim, w.n_atoms, idx)
     for k, (fn, fw, ee) in errs.items():
