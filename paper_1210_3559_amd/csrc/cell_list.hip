@@ -3,9 +3,11 @@
 // The paper evaluates all pairs and calls a cutoff future work (Sec. 2,
 // "Computational approach", last paragraphs); this variant truncates both
 // power sums at rc and shifts them to zero there, and finds the pairs with
-// r < rc through a cell list rebuilt every step.
+// r < rc through a cell list with a skin: cells of edge >= rl = rc + skin and
+// per-atom lists of the candidates within rl, rebuilt once an atom has moved
+// half the skin.
 //
-// Build (every step, every cluster independently, free boundaries):
+// Build (when due, every cluster independently, free boundaries):
 //   bbox    per chunk of 1024 atoms of a cluster: min/max, merged per
 //           cluster with 64-bit integer atomics on an order-preserving
 //           encoding (exact, so the order does not matter);
@@ -24,9 +26,10 @@
 // the 27 neighbouring cells (9 contiguous x-rows of the sorted arrays) are
 // staged in LDS, and each wavefront takes the cell's atoms one at a time
 // with its lanes across the candidates, testing them against rc before the
-// pair terms.  Every atom's sum is complete after one sweep, so the tiles of
-// the all-pairs plan are finished by the same reduce kernels with one slot
-// per tile.
+// pair terms.  Every atom's sum is complete after one sweep, so the sweep
+// finishes its atoms itself (density: rho, P and the embedding energy; force:
+// F and the kick), and the force sweep stores the cell's energy and v^2 sums,
+// added in a fixed order, in the cell's slot of the per-cluster sums.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -47,7 +50,8 @@ struct CellGrid {
 };
 
 struct CellList {
-    int nclusters = 0, natoms = 0, total_cap = 0, tile = 0, tile_shift = 0;
+    int nclusters = 0, natoms = 0, total_cap = 0;
+    std::vector<int> cap_base, cap_n;  // per cluster: first cell and cell capacity (host)
     double rc = 0.0;
     double skin = 0.0;            // list margin: cells and lists cover rl = rc + skin
     double rl = 0.0;
@@ -68,12 +72,13 @@ struct CellList {
     long long *box = nullptr;     // [6 * nclusters] order-preserving encodings of min x,y,z, max x,y,z
     int4 *chunks = nullptr;       // bounding-box work: (cluster, first atom, end atom, -)
     int nchunks = 0;
-    int *pslot = nullptr;         // atom -> partial index (tile * TILE + li)
     int *atom_cluster = nullptr;  // [natoms]
     double4 *rs = nullptr;        // sorted positions (density sweep; the force sweep reads P with them
                                   // from the density finish through sperm)
     uint16_t *nbr = nullptr;      // [natoms * kCellNbrCap] per sorted atom: staged candidates within rc
     int *nbr_n = nullptr;         // [natoms] number of such candidates (written by the density sweep)
+    double *fin = nullptr;        // [4 * natoms] per sorted atom: the sweep's sums, read back by its finish
+    double *emb = nullptr;        // [natoms] per sorted atom: embedding energy (density finish -> force finish)
 };
 
 namespace {
@@ -93,68 +98,16 @@ hipError_t dalloc(T **p, size_t n) {
 constexpr int kBBoxBlock = 256;
 constexpr int kBBoxChunk = 1024;  // atoms per bounding-box workgroup
 
-// Doubles compared as signed 64-bit integers: flip the magnitude bits of
-// negative values (an involution, so the same map decodes).
-__device__ __forceinline__ long long ord_encode(double d) {
-    const long long b = __double_as_longlong(d);
-    return b >= 0 ? b : b ^ 0x7FFFFFFFFFFFFFFFLL;
-}
-__device__ __forceinline__ double ord_decode(long long b) {
-    return __longlong_as_double(b >= 0 ? b : b ^ 0x7FFFFFFFFFFFFFFFLL);
-}
-
-// Partial bounding boxes: one workgroup per chunk of at most kBBoxChunk
-// atoms of one cluster; min/max are exact, so neither the reduction order
-// nor the atomic merge order matters.
-//
-// The same pass checks the lists of the last build: when an atom has moved
-// more than half the skin since then (|r - ref|^2 > thr2; thr2 < 0: every
-// step), two atoms may have come closer than rc without being listed, and
-// the flag asks for a rebuild.  It also copies the positions into the cell
-// order of the last build (rs), which the density sweep stages.
+// Partial bounding boxes and the check of the lists of the last build (see
+// CellCheck), for evaluations whose positions no drift kernel checked: one
+// workgroup per chunk of at most kBBoxChunk atoms of one cluster.
 __global__ __launch_bounds__(kBBoxBlock) void k_cell_bbox(const int4 *__restrict__ chunks,
-                                                          const double4 *__restrict__ rp,
-                                                          long long *__restrict__ box,
-                                                          const double4 *__restrict__ ref, double thr2,
-                                                          const int *__restrict__ slot_of,
-                                                          double4 *__restrict__ rs, int *__restrict__ flag) {
-    __shared__ double sh[6][kBBoxBlock / 64];
+                                                          const double4 *__restrict__ rp, CellCheck cc) {
+    __shared__ double sh[6 * (kBBoxBlock / 64)];
     const int4 ch = chunks[blockIdx.x];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double m[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-    bool moved = false;
-    for (int i = ch.y + threadIdx.x; i < ch.z; i += kBBoxBlock) {
-        const double4 q = rp[i];
-        const double4 o = ref[i];
-        const double ex = q.x - o.x, ey = q.y - o.y, ez = q.z - o.z;
-        moved = moved || !(ex * ex + ey * ey + ez * ez <= thr2);
-        rs[slot_of[i]] = q;
-        m[0] = fmin(m[0], q.x);
-        m[1] = fmin(m[1], q.y);
-        m[2] = fmin(m[2], q.z);
-        m[3] = fmax(m[3], q.x);
-        m[4] = fmax(m[4], q.y);
-        m[5] = fmax(m[5], q.z);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            m[d] = fmin(m[d], __shfl_xor(m[d], o, 64));
-            m[3 + d] = fmax(m[3 + d], __shfl_xor(m[3 + d], o, 64));
-        }
-    }
-    if (__ballot(moved) != 0ull && lane == 0) atomicOr(flag, 1);
-    if (lane == 0)
-        for (int d = 0; d < 6; ++d) sh[d][w] = m[d];
-    __syncthreads();
-    if (threadIdx.x < 6) {
-        const int d = threadIdx.x;
-        double v = sh[d][0];
-        for (int k = 1; k < kBBoxBlock / 64; ++k) v = d < 3 ? fmin(v, sh[d][k]) : fmax(v, sh[d][k]);
-        if (d < 3) atomicMin(&box[6 * ch.x + d], ord_encode(v));
-        else atomicMax(&box[6 * ch.x + d], ord_encode(v));
-    }
+    CellBox b;
+    for (int i = ch.y + threadIdx.x; i < ch.z; i += kBBoxBlock) cell_check_atom(cc, i, rp[i], b);
+    cell_check_merge<kBBoxBlock>(cc, ch.x, b, sh);
 }
 
 // Reset the bounding-box accumulators (min slots to +inf, max slots to -inf).
@@ -453,12 +406,13 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
                                                                 const int *__restrict__ start,
                                                                 const double4 *__restrict__ rs,
                                                                 const int *__restrict__ sperm,
-                                                                const int *__restrict__ pslot,
-                                                                double *__restrict__ part, int tile_shift,
+                                                                double *__restrict__ fin,
+                                                                double *__restrict__ emb,
                                                                 uint16_t *__restrict__ nbr,
                                                                 int *__restrict__ nbr_n,
                                                                 const double4 *__restrict__ xp, PotConst pc,
-                                                                int *__restrict__ flag, double rl2) {
+                                                                int *__restrict__ flag, double rl2,
+                                                                DensityOut dout, ForceOut fout, int finish) {
     constexpr int Q = FORCE ? 4 : 1;
     // staged candidates as four arrays (x, y, z, w): lanes reading
     // consecutive candidates touch consecutive 8-byte words, conflict-free
@@ -476,9 +430,19 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
     const int cell = corder[blockIdx.x];
     const CellGrid g = grid[cell_cluster[cell]];
     const int local = cell - g.base;
-    if (local >= g.nx * g.ny * g.nz) return;  // uniform per workgroup
-    const int s0 = start[cell], cnt = start[cell + 1] - s0;
-    if (cnt == 0) return;
+    const int s0 = start[cell], cnt = local < g.nx * g.ny * g.nz ? start[cell + 1] - s0 : 0;
+    // the cell's slot of the cluster sums (embedding energy, pair energy,
+    // v^2), stored by the force sweep; cells without atoms, also those
+    // beyond this build's grid, hold zeros
+    if (cnt == 0) {  // uniform per workgroup
+        if (FORCE && finish && threadIdx.x == 0) {
+            double *const cell_sums = fout.tile_sums + (size_t)cell * kTileSums;
+            cell_sums[0] = 0.0;
+            cell_sums[1] = 0.0;
+            cell_sums[2] = 0.0;
+        }
+        return;
+    }
     const int ix = local % g.nx, iy = (local / g.nx) % g.ny, iz = local / (g.nx * g.ny);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid < 9) {
@@ -527,7 +491,6 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
         }
     }
     __syncthreads();
-    const int tile = 1 << tile_shift;
     const float Af = (float)pc.A;
     // the own cell lies in the own row (segment 4): atom k is candidate
     // seg_off[4] + (k - seg_lo[4])
@@ -613,31 +576,69 @@ __global__ __launch_bounds__(64 * kCellWaves) void k_cell_sweep(const CellGrid *
         if constexpr (FORCE) unscale_force<PREC, GEN>(acc[0], acc[1], acc[2], acc[3]);
 #pragma unroll
         for (int q = 0; q < Q; ++q) acc[q] = wave_total(acc[q]);
+        if (lane == 0 && finish) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) fin[(size_t)k * 4 + q] = acc[q];
+        }
+    }
+    if (!finish) return;
+    // Finish: thread a takes the cell's atoms a, a + 1024, ... (their sums,
+    // stored above by the wavefronts of this workgroup, are visible after
+    // the barrier), so the loads of the per-atom epilogue are issued once per
+    // cell rather than on every wavefront's path.
+    __syncthreads();
+    if constexpr (!FORCE) {
+        // the embedding energies wait per sorted atom for the force sweep,
+        // which adds them into the cell's sums (no reduction here: it would
+        // hold every wavefront of the cell until the finish is done)
+        for (int a = tid; a < cnt; a += 64 * kCellWaves) {
+            const int k = s0 + a;
+            emb[k] = density_atom(sperm[k], fin[(size_t)k * 4], dout, pc);
+        }
+    } else {
+        // the cell's sums: each wavefront's in a fixed order (DPP), then the
+        // wavefronts' in order
+        double se = 0.0, sp = 0.0, sv = 0.0;
+        for (int a = tid; a < cnt; a += 64 * kCellWaves) {
+            const int k = s0 + a;
+            const double *t = fin + (size_t)k * 4;
+            se += emb[k];
+            force_atom(sperm[k], t[0], t[1], t[2], t[3], fout, pc, sp, sv);
+        }
+        se = wave_total(se);
+        sp = wave_total(sp);
+        sv = wave_total(sv);
+        __shared__ double wsh[3][kCellWaves];
         if (lane == 0) {
-            const int ps = pslot[sperm[k]];
-            if constexpr (FORCE) {
-                const int t = ps >> tile_shift, li = ps & (tile - 1);
-                double *out = part + (size_t)t * 4 * tile + li;
-                out[0] = acc[0];
-                out[tile] = acc[1];
-                out[2 * tile] = acc[2];
-                out[3 * tile] = acc[3];
-            } else {
-                part[ps] = acc[0];
+            wsh[0][wave] = se;
+            wsh[1][wave] = sp;
+            wsh[2][wave] = sv;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double e = 0.0, p = 0.0, v2 = 0.0;
+            for (int w = 0; w < kCellWaves; ++w) {
+                e += wsh[0][w];
+                p += wsh[1][w];
+                v2 += wsh[2][w];
             }
+            double *const cell_sums = fout.tile_sums + (size_t)cell * kTileSums;
+            cell_sums[0] = e;
+            cell_sums[1] = p;
+            cell_sums[2] = v2;
         }
     }
 }
 
 template <bool FORCE>
-hipError_t launch_cell_sweep(CellList *cl, double *part, const double4 *xp, const PotConst &pc, int precision,
-                             hipStream_t s) {
+hipError_t launch_cell_sweep(CellList *cl, const double4 *xp, const DensityOut &dout, const ForceOut &fout,
+                             int finish, const PotConst &pc, int precision, hipStream_t s) {
     (void)hipGetLastError();
     const dim3 grid(cl->total_cap), block(64 * kCellWaves);
     const size_t lds = kCellStage * sizeof(double4);
 #define SCMD_CELL_ARGS                                                                                          \
-    cl->grid, cl->corder, cl->cell_cluster, cl->start, cl->rs, cl->sperm, cl->pslot, part, cl->tile_shift, cl->nbr, \
-        cl->nbr_n, xp, pc, cl->flag, cl->rl * cl->rl
+    cl->grid, cl->corder, cl->cell_cluster, cl->start, cl->rs, cl->sperm, cl->fin, cl->emb, cl->nbr, cl->nbr_n, xp, \
+        pc, cl->flag, cl->rl * cl->rl, dout, fout, finish
     if (precision == SCMD_FP64) {
         if (pc.generic)
             hipLaunchKernelGGL((k_cell_sweep<SCMD_FP64, true, FORCE>), grid, block, lds, s, SCMD_CELL_ARGS);
@@ -668,9 +669,9 @@ CellList *cell_list_create() {
 void cell_list_destroy(CellList *cl) {
     if (!cl) return;
     void *ptrs[] = {cl->grid0, cl->grid,  cl->cell_cluster, cl->count,  cl->start, cl->cursor,
-                    cl->cell_of, cl->perm, cl->sperm, cl->box, cl->chunks, cl->pslot,
+                    cl->cell_of, cl->perm, cl->sperm, cl->box, cl->chunks,
                     cl->atom_cluster, cl->rs, cl->nbr, cl->nbr_n, cl->corder, cl->ref,
-                    cl->slot_of, cl->flag, cl->nbuilds};
+                    cl->slot_of, cl->flag, cl->nbuilds, cl->fin, cl->emb};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete cl;
@@ -696,7 +697,7 @@ static hipError_t set_cell_sweep_lds() {
 }
 
 hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, double rc, double skin,
-                          const double4 *rp_dev, const ITile *tiles, int ntiles, int tile) {
+                          const double4 *rp_dev) {
     if (hipError_t e0 = set_cell_sweep_lds(); e0 != hipSuccess) return e0;
     const int natoms = (int)offsets[nclusters];
     cl->nclusters = nclusters;
@@ -705,10 +706,6 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
     cl->skin = skin;
     cl->rl = rc + skin;
     rc = cl->rl;  // cells cover the list radius
-    cl->tile = tile;
-    cl->tile_shift = 0;
-    while ((1 << cl->tile_shift) < tile) ++cl->tile_shift;
-    if ((1 << cl->tile_shift) != tile) return hipErrorInvalidValue;
     std::vector<double4> r(natoms);
     hipError_t e;
     if (natoms > 0 && (e = hipMemcpy(r.data(), rp_dev, natoms * sizeof(double4), hipMemcpyDeviceToHost)) != hipSuccess)
@@ -718,6 +715,8 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
     // side before the grid coarsens), at most 1024
     std::vector<CellGrid> grids(nclusters);
     std::vector<int> cell_cluster;
+    cl->cap_base.assign(nclusters, 0);
+    cl->cap_n.assign(nclusters, 0);
     int base = 0;
     for (int c = 0; c < nclusters; ++c) {
         CellGrid g{};
@@ -743,6 +742,8 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
         g.hx = g.hy = g.hz = rc;
         g.base = base;
         const int ncap = cap[0] * cap[1] * cap[2];
+        cl->cap_base[c] = base;
+        cl->cap_n[c] = ncap;
         cell_cluster.insert(cell_cluster.end(), ncap, c);
         base += ncap;
         grids[c] = g;
@@ -753,12 +754,9 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
         for (int a = (int)offsets[c]; a < (int)offsets[c + 1]; a += kBBoxChunk)
             chunks.push_back(make_int4(c, a, std::min<int>(a + kBBoxChunk, (int)offsets[c + 1]), 0));
     cl->nchunks = (int)chunks.size();
-    std::vector<int> pslot(natoms), ac(natoms);
-    for (int t = 0; t < ntiles; ++t)
-        for (int li = 0; li < tiles[t].ni; ++li) {
-            pslot[tiles[t].i0 + li] = t * tile + li;
-            ac[tiles[t].i0 + li] = tiles[t].c;
-        }
+    std::vector<int> ac(natoms);
+    for (int c = 0; c < nclusters; ++c)
+        for (int i = (int)offsets[c]; i < (int)offsets[c + 1]; ++i) ac[i] = c;
     if ((e = dalloc(&cl->grid, nclusters)) != hipSuccess) return e;
     if ((e = dalloc(&cl->grid0, nclusters)) != hipSuccess) return e;
     if ((e = dalloc(&cl->cell_cluster, base)) != hipSuccess) return e;
@@ -779,11 +777,12 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
     if (base > 0) hipLaunchKernelGGL(k_cell_clear, dim3((base + 255) / 256), dim3(256), 0, 0, cl->count, base);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
-    if ((e = dalloc(&cl->pslot, natoms)) != hipSuccess) return e;
     if ((e = dalloc(&cl->atom_cluster, natoms)) != hipSuccess) return e;
     if ((e = dalloc(&cl->rs, natoms)) != hipSuccess) return e;
     if ((e = dalloc(&cl->nbr, (size_t)natoms * kCellNbrCap)) != hipSuccess) return e;
     if ((e = dalloc(&cl->nbr_n, natoms)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->fin, 4 * (size_t)natoms)) != hipSuccess) return e;
+    if ((e = dalloc(&cl->emb, natoms)) != hipSuccess) return e;
     if ((e = dalloc(&cl->ref, natoms)) != hipSuccess) return e;
     if ((e = dalloc(&cl->slot_of, natoms)) != hipSuccess) return e;
     if ((e = dalloc(&cl->flag, 1)) != hipSuccess) return e;
@@ -809,23 +808,30 @@ hipError_t cell_list_plan(CellList *cl, int nclusters, const int64_t *offsets, d
             return e;
         if ((e = hipMemcpy(cl->slot_of, ident.data(), natoms * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
             return e;
-        if ((e = hipMemcpy(cl->pslot, pslot.data(), natoms * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
-            return e;
         if ((e = hipMemcpy(cl->atom_cluster, ac.data(), natoms * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
             return e;
     }
     return hipSuccess;
 }
 
-hipError_t cell_list_build(CellList *cl, const double4 *rp, hipStream_t s) {
+// rebuild once an atom has moved half the skin (every step without one)
+static double check_thr2(const CellList *cl) {
+    const double half = 0.5 * cl->skin;
+    return cl->skin > 0.0 ? half * half : -1.0;
+}
+
+CellCheck cell_list_check(CellList *cl) {
+    return CellCheck{cl->ref, cl->slot_of, cl->rs, cl->box, cl->flag, check_thr2(cl)};
+}
+
+hipError_t cell_list_build(CellList *cl, const double4 *rp, bool checked, hipStream_t s) {
     (void)hipGetLastError();
     const int na = cl->natoms, tc = cl->total_cap;
-    // rebuild once an atom has moved half the skin (every step without one)
-    const double half = 0.5 * cl->skin;
-    const double thr2 = cl->skin > 0.0 ? half * half : -1.0;
-    if (cl->nchunks > 0)
-        hipLaunchKernelGGL(k_cell_bbox, dim3(cl->nchunks), dim3(kBBoxBlock), 0, s, cl->chunks, rp, cl->box, cl->ref,
-                           thr2, cl->slot_of, cl->rs, cl->flag);
+    const double thr2 = check_thr2(cl);
+    if (!checked && cl->nchunks > 0) {
+        const CellCheck cc{cl->ref, cl->slot_of, cl->rs, cl->box, cl->flag, thr2};
+        hipLaunchKernelGGL(k_cell_bbox, dim3(cl->nchunks), dim3(kBBoxBlock), 0, s, cl->chunks, rp, cc);
+    }
     if (na > 0)
         hipLaunchKernelGGL(k_cell_count, dim3((na + 255) / 256), dim3(256), 0, s, cl->grid0, cl->grid, cl->box, cl->rl,
                            cl->atom_cluster, rp, cl->sperm, cl->cell_of, cl->count, na, cl->flag);
@@ -861,34 +867,39 @@ hipError_t cell_list_get_ref(CellList *cl, double4 *host_out) {
     return hipMemcpy(host_out, cl->ref, cl->natoms * sizeof(double4), hipMemcpyDeviceToHost);
 }
 
-hipError_t cell_list_restore(CellList *cl, const double4 *ref_host, double4 *scratch_dev, const SweepBuffers &B,
-                             const PotConst &pc, int precision, hipStream_t s) {
+hipError_t cell_list_restore(CellList *cl, const double4 *ref_host, double4 *scratch_dev, const PotConst &pc,
+                             int precision, hipStream_t s) {
     if (cl->natoms == 0) return cell_list_invalidate(cl, s);
     hipError_t e = hipMemcpyAsync(scratch_dev, ref_host, cl->natoms * sizeof(double4), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
     // cells and lists of the positions of the last build, as that build made
     // them: a build forced from those positions, then a density sweep that
-    // lists the candidates (its sums are scratch, overwritten by the next
-    // evaluation)
+    // lists the candidates and finishes no atom
     if ((e = cell_list_invalidate(cl, s)) != hipSuccess) return e;
-    if ((e = cell_list_build(cl, scratch_dev, s)) != hipSuccess) return e;
-    if ((e = launch_cell_sweep<false>(cl, B.part, nullptr, pc, precision, s)) != hipSuccess) return e;
+    if ((e = cell_list_build(cl, scratch_dev, false, s)) != hipSuccess) return e;
+    if ((e = launch_cell_sweep<false>(cl, nullptr, DensityOut{}, ForceOut{}, 0, pc, precision, s)) != hipSuccess)
+        return e;
     // the density sweep left the flag set: clear it (the lists hold)
     return hipMemcpyAsync(cl->flag, &kFlagClear, sizeof(int), hipMemcpyHostToDevice, s);
 }
 
-hipError_t cell_list_density(CellList *cl, const SweepBuffers &B, const ITile *tiles, int ntiles, int tile,
-                             const PotConst &pc, int precision, hipStream_t s) {
-    hipError_t e = launch_cell_sweep<false>(cl, B.part, nullptr, pc, precision, s);
-    if (e != hipSuccess) return e;
-    return launch_density_reduce(tiles, ntiles, tile, B, pc, 1, s);
+hipError_t cell_list_density(CellList *cl, const SweepBuffers &B, const PotConst &pc, int precision,
+                             hipStream_t s) {
+    const DensityOut o{B.rp, B.xp, B.rho, B.tile_sums};
+    return launch_cell_sweep<false>(cl, nullptr, o, ForceOut{}, 1, pc, precision, s);
 }
 
-hipError_t cell_list_force(CellList *cl, const SweepBuffers &B, const StepArgs &a, const ITile *tiles, int ntiles,
-                           int tile, const PotConst &pc, int precision, hipStream_t s) {
-    hipError_t e = launch_cell_sweep<true>(cl, B.part, B.xp, pc, precision, s);
-    if (e != hipSuccess) return e;
-    return launch_force_reduce(tiles, ntiles, tile, B, a, pc, 1, s);
+hipError_t cell_list_force(CellList *cl, const SweepBuffers &B, const StepArgs &a, const PotConst &pc,
+                           int precision, hipStream_t s) {
+    const ForceOut fo{B.f, B.v, B.tile_sums, a.h, a.advance};
+    return launch_cell_sweep<true>(cl, B.xp, DensityOut{}, fo, 1, pc, precision, s);
 }
+
+void cell_list_sum_slots(const CellList *cl, int cluster, int *first, int *count) {
+    *first = cl->cap_base[cluster];
+    *count = cl->cap_n[cluster];
+}
+
+int cell_list_total_slots(const CellList *cl) { return cl->total_cap; }
 
 }  // namespace scmd

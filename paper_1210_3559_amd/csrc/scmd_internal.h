@@ -117,6 +117,21 @@ struct SweepBuffers {
     double2 *dpv;       // row sweeps of one cluster: drift inputs (p = r + dt h F, v), 3 pairs per atom
 };
 
+// The cell list's per-step check, run by whichever kernel last moved the
+// atoms: an atom that has moved more than half the skin since the last
+// build (|r - ref|^2 > thr2; thr2 < 0: every step) sets *flag; the
+// positions are copied into that build's cell order (rs[slot_of[i]]); the
+// cluster's bounding box is merged into box (6 order-preserving encodings
+// per cluster: min x, y, z, max x, y, z).
+struct CellCheck {
+    const double4 *ref;
+    const int *slot_of;
+    double4 *rs;
+    long long *box;
+    int *flag;
+    double thr2;
+};
+
 struct StepArgs {
     const ClusterDesc *cd;
     ClusterState *st;
@@ -221,8 +236,10 @@ hipError_t launch_bath_prep(const StepArgs &a, const int32_t *atom_cluster, cons
 hipError_t launch_finalize(const StepArgs &a, const double *tile_sums, int nclusters, int step_add, hipStream_t s);
 // Single cluster: the finish of the run's step `local` (>= 1, counted from the
 // start of the run, counter not stored) fused with the drift of step local+1.
+// cc (nullptr: none): the cell list's check on the drifted positions of the
+// single cluster.
 hipError_t launch_drift_fin(const StepArgs &a, const double *tile_sums, int local, double4 *rp, double4 *v,
-                            const double4 *f, int natoms, hipStream_t s);
+                            const double4 *f, int natoms, const CellCheck *cc, hipStream_t s);
 
 
 // Drift of every atom: v <- lambda v + (dt/2m) F, then r <- r + dt v, or

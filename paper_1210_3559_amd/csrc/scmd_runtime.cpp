@@ -665,10 +665,15 @@ int ensure_plan(scmd_ctx *c) {
     if (c->neighbour == SCMD_CELLLIST) {
         if (!c->cells) c->cells = cell_list_create();
         if (!c->cells) return fail(c, SCMD_ENOMEM, "cell list allocation failed");
-        hipError_t e = cell_list_plan(c->cells, c->nclusters, c->offsets.data(), c->params.rc, c->cell_skin, c->rp.p,
-                                      tiles.data(), c->ntiles, c->tile);
-        if (e == hipSuccess) e = hipMemset(c->d_part.p, 0, c->d_part.n * sizeof(double));
+        hipError_t e = cell_list_plan(c->cells, c->nclusters, c->offsets.data(), c->params.rc, c->cell_skin, c->rp.p);
         if (e != hipSuccess) return fail(c, SCMD_EDEVICE, std::string("cell list plan: ") + hipGetErrorString(e));
+        // the cell sweeps finish their atoms and store per-cell sums: a
+        // cluster's totals add its cells' slots
+        for (int k = 0; k < c->nclusters; ++k)
+            cell_list_sum_slots(c->cells, k, &c->cdesc[k].tile0, &c->cdesc[k].ntiles);
+        HIP_TRY(c, c->d_tile_sums.ensure(std::max<size_t>((size_t)cell_list_total_slots(c->cells) * kTileSums, 1)));
+        HIP_TRY(c, hipMemset(c->d_tile_sums.p, 0, c->d_tile_sums.n * sizeof(double)));
+        HIP_TRY(c, upload_cdesc(c));
     }
     return SCMD_OK;
 }
@@ -737,8 +742,8 @@ hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int adv
         e = force ? launch_row_force(R, B, A, fused, local, bath, c->pc, c->precision, s)
                   : launch_row_density(R, B, A, RowDrift{drift_mode, local, bath}, c->pc, c->precision, s);
     } else if (c->neighbour == SCMD_CELLLIST) {
-        e = force ? cell_list_force(c->cells, B, A, c->d_tiles.p, c->ntiles, c->tile, c->pc, c->precision, s)
-                  : cell_list_density(c->cells, B, c->d_tiles.p, c->ntiles, c->tile, c->pc, c->precision, s);
+        e = force ? cell_list_force(c->cells, B, A, c->pc, c->precision, s)
+                  : cell_list_density(c->cells, B, c->pc, c->precision, s);
     } else {
         SweepLaunch L{c->d_items.p, c->d_order.p, c->d_tiles.p, c->nitems, c->ipt, c->wi, c->wj};
         e = force ? launch_force(L, B, A, c->pc, c->precision, s) : launch_density(L, B, c->pc, c->precision, s);
@@ -756,7 +761,9 @@ hipError_t sweep(scmd_ctx *c, bool force, hipStream_t s, bool capturing, int adv
 // runs the thermostat (second half of a step).
 // Sweeps and tile finishes of one force evaluation (everything but the
 // per-cluster finalize).
-hipError_t enqueue_sweeps(scmd_ctx *c, hipStream_t s, bool capturing, int advance, int energy = 1) {
+// checked: this step's drift ran the cell list's check (single cluster).
+hipError_t enqueue_sweeps(scmd_ctx *c, hipStream_t s, bool capturing, int advance, int energy = 1,
+                          bool checked = false) {
     hipError_t e;
     const SweepBuffers B = buffers(c);
     const StepArgs A = step_args(c, advance, energy);
@@ -769,7 +776,7 @@ hipError_t enqueue_sweeps(scmd_ctx *c, hipStream_t s, bool capturing, int advanc
         return launch_sym_force(L, B, A, c->pc, c->precision, 1, s);
     }
     if (c->neighbour == SCMD_CELLLIST) {
-        if ((e = cell_list_build(c->cells, c->rp.p, s)) != hipSuccess) return e;
+        if ((e = cell_list_build(c->cells, c->rp.p, checked, s)) != hipSuccess) return e;
     }
     if ((e = sweep(c, false, s, capturing, advance)) != hipSuccess) return e;
     if (c->has_split && (e = launch_density_reduce(c->d_tiles.p, c->ntiles, c->tile, B, c->pc, 2, s)) != hipSuccess)
@@ -823,16 +830,21 @@ hipError_t enqueue_run(scmd_ctx *c, hipStream_t s, bool capturing, int64_t nstep
         return hipSuccess;
     }
     const bool fuse = c->nclusters == 1;
+    const bool cells = c->neighbour == SCMD_CELLLIST;
+    CellCheck cc{};
+    if (fuse && cells) cc = cell_list_check(c->cells);
     for (int64_t k = 0; k < nsteps; ++k) {
         // a batch stores the step counters after every step (local = 0)
-        if (fuse && k > 0)
-            e = launch_drift_fin(A, c->d_tile_sums.p, (int)k, c->rp.p, c->v.p, c->f.p, c->natoms, s);
+        const bool fin = fuse && k > 0;
+        if (fin)
+            e = launch_drift_fin(A, c->d_tile_sums.p, (int)k, c->rp.p, c->v.p, c->f.p, c->natoms, cells ? &cc : nullptr,
+                                 s);
         else
             e = launch_drift(c->atom_cluster.p, c->d_cdesc.p, c->d_state.p, c->rp.p, c->v.p, c->f.p, c->natoms,
                              c->mass, c->dt, half_kick(c), 0, s);
         if (e != hipSuccess) return e;
         if (capturing) c->capture_sample = (k == std::max<int64_t>(0, nsteps - 2));
-        e = enqueue_sweeps(c, s, capturing, 1, k == nsteps - 1);
+        e = enqueue_sweeps(c, s, capturing, 1, k == nsteps - 1, fin && cells);
         if (e != hipSuccess) return e;
         if (!fuse && (e = launch_finalize(A, c->d_tile_sums.p, c->nclusters, 1, s)) != hipSuccess) return e;
     }
@@ -1825,8 +1837,8 @@ int scmd_set_state(scmd_ctx *ctx, const void *buf, size_t bytes) {
             for (size_t k = 0; k < 4 * (size_t)ctx->natoms && !have_ref; ++k) have_ref = ((const double *)p)[k] != 0.0;
             if (have_ref) {
                 HIP_TRY(ctx, ctx->restore_scratch.ensure(std::max(ctx->natoms, 1)));
-                HIP_TRY(ctx, cell_list_restore(ctx->cells, (const double4 *)p, ctx->restore_scratch.p, buffers(ctx),
-                                               ctx->pc, ctx->precision, ctx->stream));
+                HIP_TRY(ctx, cell_list_restore(ctx->cells, (const double4 *)p, ctx->restore_scratch.p, ctx->pc,
+                                               ctx->precision, ctx->stream));
             } else {
                 HIP_TRY(ctx, cell_list_invalidate(ctx->cells, ctx->stream));
             }

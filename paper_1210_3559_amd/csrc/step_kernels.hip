@@ -80,26 +80,33 @@ __global__ __launch_bounds__(256) void k_bath_prep(const int32_t *__restrict__ a
 // Drift fused with the finish of the previous step of a single cluster:
 // every workgroup reduces the cluster's tile sums itself (same order, so the
 // same thermostat factor in every workgroup) and workgroup 0 stores the
-// cluster state, which saves a launch per step.
+// cluster state, which saves a launch per step.  CELL: the cell list's
+// check on the drifted positions as well (another launch saved).
+template <bool CELL>
 __global__ __launch_bounds__(256) void k_drift_fin(dev::FinalizeArgs fa, double4 *__restrict__ rp,
                                                    double4 *__restrict__ v, const double4 *__restrict__ f,
-                                                   int natoms, double dt, double h) {
+                                                   int natoms, double dt, double h, CellCheck cc) {
     __shared__ double sh[12];
+    __shared__ double sh_box[6 * (256 / 64)];
     __shared__ double lam_sh;
     const double l0 = dev::cluster_finalize(0, fa, sh, blockIdx.x == 0);
     if (threadIdx.x == 0) lam_sh = l0;
     __syncthreads();
     const double lam = lam_sh;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= natoms) return;
-    const ClusterDesc &d = fa.cd[0];
-    double4 vi = v[i];
-    const double4 fi = f[i];
-    double4 ri = rp[i];
-    // this drift starts step fa.step_add + 1 of the run
-    drift_atom(d, fa.st[0].step + fa.step_add + 1, i - d.off, lam, fa.mass_u, dt, h, ri, vi, fi);
-    v[i] = vi;
-    rp[i] = ri;
+    dev::CellBox b;
+    if (i < natoms) {
+        const ClusterDesc &d = fa.cd[0];
+        double4 vi = v[i];
+        const double4 fi = f[i];
+        double4 ri = rp[i];
+        // this drift starts step fa.step_add + 1 of the run
+        drift_atom(d, fa.st[0].step + fa.step_add + 1, i - d.off, lam, fa.mass_u, dt, h, ri, vi, fi);
+        v[i] = vi;
+        rp[i] = ri;
+        if constexpr (CELL) dev::cell_check_atom(cc, i, ri, b);
+    }
+    if constexpr (CELL) dev::cell_check_merge<256>(cc, 0, b, sh_box);
 }
 
 __global__ __launch_bounds__(256) void k_sample(const ClusterState *__restrict__ st, int nclusters,
@@ -147,11 +154,16 @@ hipError_t launch_bath_prep(const StepArgs &a, const int32_t *atom_cluster, cons
 }
 
 hipError_t launch_drift_fin(const StepArgs &a, const double *tile_sums, int local, double4 *rp, double4 *v,
-                            const double4 *f, int natoms, hipStream_t s) {
+                            const double4 *f, int natoms, const CellCheck *cc, hipStream_t s) {
     if (natoms <= 0) return hipSuccess;
     const dev::FinalizeArgs fa{a.cd, a.st, tile_sums, a.flag, a.mass_u, a.dt, 1, local, 0};
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_drift_fin, dim3((natoms + 255) / 256), dim3(256), 0, s, fa, rp, v, f, natoms, a.dt, a.h);
+    if (cc)
+        hipLaunchKernelGGL(k_drift_fin<true>, dim3((natoms + 255) / 256), dim3(256), 0, s, fa, rp, v, f, natoms, a.dt,
+                           a.h, *cc);
+    else
+        hipLaunchKernelGGL(k_drift_fin<false>, dim3((natoms + 255) / 256), dim3(256), 0, s, fa, rp, v, f, natoms,
+                           a.dt, a.h, CellCheck{});
     return hipGetLastError();
 }
 

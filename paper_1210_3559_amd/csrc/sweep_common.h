@@ -391,13 +391,35 @@ __device__ __forceinline__ void cluster_totals(const ClusterDesc &d, const doubl
     emb = epair = v2 = 0.0;
     const int t = threadIdx.x;
     if (t < kTotBlock) {
-        for (int k = t; k < d.ntiles; k += kTotBlock) {
-            const double *ts = tile_sums + (size_t)(d.tile0 + k) * kTileSums;
-            if constexpr (!V2_ONLY) {
-                emb += ts[0];
-                epair += ts[1];
+        // thread t adds slots t, t + kTotBlock, ... in that order; the loads
+        // of kTotU of them are issued together (the cell list has thousands
+        // of slots per cluster)
+        constexpr int kTotU = 8;
+        for (int k0 = t; k0 < d.ntiles; k0 += kTotU * kTotBlock) {
+            double e[kTotU], p[kTotU], w[kTotU];
+#pragma unroll
+            for (int u = 0; u < kTotU; ++u) {
+                const int k = k0 + u * kTotBlock;
+                e[u] = p[u] = w[u] = 0.0;
+                if (k < d.ntiles) {
+                    const double *ts = tile_sums + (size_t)(d.tile0 + k) * kTileSums;
+                    if constexpr (!V2_ONLY) {
+                        e[u] = ts[0];
+                        p[u] = ts[1];
+                    }
+                    w[u] = ts[2];
+                }
             }
-            v2 += ts[2];
+#pragma unroll
+            for (int u = 0; u < kTotU; ++u) {
+                if (k0 + u * kTotBlock < d.ntiles) {
+                    if constexpr (!V2_ONLY) {
+                        emb += e[u];
+                        epair += p[u];
+                    }
+                    v2 += w[u];
+                }
+            }
         }
     }
     if constexpr (!V2_ONLY) {
@@ -449,6 +471,65 @@ __device__ inline double cluster_finalize(int c, const FinalizeArgs &o, double *
     }
     if (writer) o.st[c] = s;
     return s.lambda;
+}
+
+// ---------------------------------------------------------------------------
+// Cell-list check (see CellCheck): per atom, then merged per workgroup.
+// ---------------------------------------------------------------------------
+// Doubles compared as signed 64-bit integers: flip the magnitude bits of
+// negative values (an involution, so the same map decodes).
+__device__ __forceinline__ long long ord_encode(double d) {
+    const long long b = __double_as_longlong(d);
+    return b >= 0 ? b : b ^ 0x7FFFFFFFFFFFFFFFLL;
+}
+__device__ __forceinline__ double ord_decode(long long b) {
+    return __longlong_as_double(b >= 0 ? b : b ^ 0x7FFFFFFFFFFFFFFFLL);
+}
+
+struct CellBox {
+    double m[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    bool moved = false;
+};
+
+__device__ __forceinline__ void cell_check_atom(const CellCheck &cc, int i, const double4 &q, CellBox &b) {
+    const double4 o = cc.ref[i];
+    const double ex = q.x - o.x, ey = q.y - o.y, ez = q.z - o.z;
+    b.moved = b.moved || !(ex * ex + ey * ey + ez * ez <= cc.thr2);
+    cc.rs[cc.slot_of[i]] = q;
+    b.m[0] = fmin(b.m[0], q.x);
+    b.m[1] = fmin(b.m[1], q.y);
+    b.m[2] = fmin(b.m[2], q.z);
+    b.m[3] = fmax(b.m[3], q.x);
+    b.m[4] = fmax(b.m[4], q.y);
+    b.m[5] = fmax(b.m[5], q.z);
+}
+
+// Every thread of the workgroup (BLOCK threads) calls this once with its
+// accumulated box; min/max are exact, so neither the reduction order nor
+// the atomic merge order matters.  sh: 6 x BLOCK/64 doubles.
+template <int BLOCK>
+__device__ __forceinline__ void cell_check_merge(const CellCheck &cc, int cluster, CellBox &b, double *sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            b.m[d] = fmin(b.m[d], __shfl_xor(b.m[d], o, 64));
+            b.m[3 + d] = fmax(b.m[3 + d], __shfl_xor(b.m[3 + d], o, 64));
+        }
+    }
+    if (__ballot(b.moved) != 0ull && lane == 0) atomicOr(cc.flag, 1);
+    if (lane == 0)
+        for (int d = 0; d < 6; ++d) sh[d * (BLOCK / 64) + w] = b.m[d];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int d = threadIdx.x;
+        double v = sh[d * (BLOCK / 64)];
+        for (int k = 1; k < BLOCK / 64; ++k)
+            v = d < 3 ? fmin(v, sh[d * (BLOCK / 64) + k]) : fmax(v, sh[d * (BLOCK / 64) + k]);
+        if (d < 3) atomicMin(&cc.box[6 * cluster + d], ord_encode(v));
+        else atomicMax(&cc.box[6 * cluster + d], ord_encode(v));
+    }
 }
 
 }  // namespace dev
