@@ -201,7 +201,7 @@ def autotune_pick(w):
     """The autotuner's launch plan for this workload's cluster layout and
     precision (None when the table has no entry: library defaults)."""
     from paper_1210_3559_amd import autotune
-    return autotune.lookup(w.offsets, w.precision)
+    return autotune.lookup(w.offsets, w.precision, cell=w.rc > 0)
 
 
 def mixed_error(w, state, nthreads: int, max_clusters: int = 4, sample: int = 64):
@@ -364,9 +364,9 @@ def main(argv=None):
                     fw.precision = prec
                 steps = max(32, min(2000, int(2e10 / max(1, _pairs(fw.sizes())))))
                 print(f"[bench] form {key}: {fw.n_atoms} atoms, {steps} steps", file=sys.stderr, flush=True)
-                # batches run the launch plan the autotuner measured for them
-                # (paper_1210_3559_amd/tuning_cache.json)
-                tun = "auto" if fw.n_clusters > 1 else None
+                # batches run the launch plan and the cell list the skin that
+                # the autotuner measured for them (paper_1210_3559_amd/tuning_cache.json)
+                tun = "auto" if fw.n_clusters > 1 or fw.rc > 0 else None
                 r = time_gpu(fw, steps, min(64, steps), tuning=tun,
                              keep_state=fw.precision == "mixed" and not args.no_error)
                 if tun:

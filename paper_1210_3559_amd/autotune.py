@@ -1,10 +1,12 @@
-"""Launch-shape autotuner for the all-pairs sweeps.
+"""Launch-shape autotuner for the all-pairs sweeps and the cell list.
 
-For a workload it times every supported (ipt, waves_i, waves_j) shape and a
-few work-splitting targets with whole velocity-Verlet steps replayed from
-HIP graphs, and keeps the fastest.  Results are cached as JSON keyed by
-(device architecture, precision, cluster-size bucket, cluster count bucket),
-so ``Simulation(..., tuning="auto")`` can pick them up later.
+For an all-pairs workload it times every supported (ipt, waves_i, waves_j)
+shape and a few work-splitting targets with whole velocity-Verlet steps
+replayed from HIP graphs, and keeps the fastest; for a cell-list workload it
+times the list skin (``cell_skin``: a longer list against fewer rebuilds).
+Results are cached as JSON keyed by (device architecture, precision,
+cluster-size bucket, cluster count bucket, and "cell" for the cell list), so
+``Simulation(..., tuning="auto")`` can pick them up later.
 
     python -m paper_1210_3559_amd.autotune --workloads ni2243_cooling,batch256 [--cache PATH]
 """
@@ -26,15 +28,17 @@ SHAPES = [(1, 4, 1), (2, 4, 1), (1, 2, 2), (2, 2, 2), (1, 1, 4), (2, 1, 4), (1, 
 TARGETS = [1, 512, 2048, 8192]
 ROW_WAVES = [4, 8, 16]
 ROW_TARGETS = [256, 512, 1024]  # workgroups per row sweep
+CELL_SKINS = [0.2, 0.3, 0.4, 0.5, 0.6]  # A; rebuilds every step at 0, LDS stage overflow from ~0.8
 # measured on MI355X by `python -m paper_1210_3559_amd.autotune` and committed with the package
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 ARCH = "gfx950"
 
 
-def bucket(offsets, precision: str) -> str:
+def bucket(offsets, precision: str, cell: bool = False) -> str:
     sizes = np.diff(np.asarray(offsets))
     nmax = int(sizes.max()) if len(sizes) else 0
-    return f"{ARCH}/{precision}/nmax2^{max(0, math.ceil(math.log2(max(nmax, 1))))}/nc2^{math.ceil(math.log2(max(len(sizes), 1)))}"
+    key = f"{ARCH}/{precision}/nmax2^{max(0, math.ceil(math.log2(max(nmax, 1))))}/nc2^{math.ceil(math.log2(max(len(sizes), 1)))}"
+    return key + "/cell" if cell else key
 
 
 def _time(sim: "scmd.Simulation", steps: int) -> float:
@@ -45,24 +49,28 @@ def _time(sim: "scmd.Simulation", steps: int) -> float:
 
 def tune(w, precision: str | None = None, budget_s: float = 0.25, shapes=SHAPES, targets=TARGETS, verbose=True,
          symmetric: bool = True, row: bool = True):
-    """Time every shape/target on workload w; returns (best tuning dict, table)."""
+    """Time every shape/target (cell list: every skin) on workload w; returns
+    (best tuning dict, table)."""
     precision = precision or w.precision
     pairs = float(np.sum(w.sizes().astype(np.float64) ** 2))
     table = []
-    candidates = candidate_plans(w.sizes(), shapes, targets, symmetric, row)
-    for cand, tgts in candidates:
-        for tgt in tgts:
-            tun = dict(cand, target_items=tgt)
-            with scmd.Simulation.from_workload(w, precision=precision, tuning=tun) as sim:
-                sim.step(32)
-                dt1 = _time(sim, 32)
-                steps = int(max(32, min(4096, budget_s / max(dt1, 1e-7))))
-                steps = 32 * max(1, steps // 32)
-                dt = _time(sim, steps)
-            table.append(dict(tuning=tun, ms_per_step=1e3 * dt))
-            if verbose:
-                print(f"[tune] {w.name} {precision} {tun} {1e3 * dt:.4f} ms/step "
-                      f"({pairs / dt / 1e9:.1f} G ordered pairs/s)", file=sys.stderr, flush=True)
+    if w.rc > 0:
+        tunings = [dict(cell_skin=s) for s in CELL_SKINS]
+    else:
+        tunings = [dict(cand, target_items=tgt) for cand, tgts in candidate_plans(w.sizes(), shapes, targets,
+                                                                                  symmetric, row) for tgt in tgts]
+    for tun in tunings:
+        with scmd.Simulation.from_workload(w, precision=precision, tuning=tun) as sim:
+            sim.step(32)
+            dt1 = _time(sim, 32)
+            steps = int(max(32, min(4096, budget_s / max(dt1, 1e-7))))
+            steps = 32 * max(1, steps // 32)
+            dt = _time(sim, steps)
+        table.append(dict(tuning=tun, ms_per_step=1e3 * dt))
+        if verbose:
+            rate = (f"{w.n_atoms / dt:.4g} atom-steps/s" if w.rc > 0 else
+                    f"{pairs / dt / 1e9:.1f} G ordered pairs/s")
+            print(f"[tune] {w.name} {precision} {tun} {1e3 * dt:.4f} ms/step ({rate})", file=sys.stderr, flush=True)
     best = min(table, key=lambda r: r["ms_per_step"])
     return best["tuning"], table
 
@@ -95,9 +103,9 @@ def load_cache(path: str = DEFAULT_CACHE) -> dict:
     return {}
 
 
-def lookup(offsets, precision: str, path: str = DEFAULT_CACHE):
-    """Cached tuning for this cluster layout, or None."""
-    entry = load_cache(path).get(bucket(offsets, precision))
+def lookup(offsets, precision: str, path: str = DEFAULT_CACHE, cell: bool = False):
+    """Cached tuning for this cluster layout (cell: the cell-list variant), or None."""
+    entry = load_cache(path).get(bucket(offsets, precision, cell))
     return None if entry is None else dict(entry["tuning"])
 
 
@@ -116,7 +124,7 @@ def main(argv=None):
         w = inputs.by_name(name)
         prec = args.precision or w.precision
         best, table = tune(w, prec, args.budget)
-        key = bucket(w.offsets, prec)
+        key = bucket(w.offsets, prec, w.rc > 0)
         cache[key] = dict(tuning=best, ms_per_step=min(r["ms_per_step"] for r in table), workload=w.name)
         report[w.name] = dict(key=key, best=best, table=table)
         print(json.dumps(dict(workload=w.name, key=key, best=best, ms=cache[key]["ms_per_step"])), flush=True)

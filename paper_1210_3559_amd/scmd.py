@@ -411,9 +411,13 @@ class Simulation:
                                 SCMD_CELLLIST if p["rc"] > 0 else SCMD_ALLPAIRS)
             if tuning == "auto":
                 from . import autotune
-                tuning = autotune.lookup(offsets, precision)
+                tuning = autotune.lookup(offsets, precision, cell=p["rc"] > 0)
             if tuning:
-                scmd_set_tuning(self.ctx, **tuning)
+                tuning = dict(tuning)
+                if "cell_skin" in tuning:
+                    scmd_set_cell_skin(self.ctx, tuning.pop("cell_skin"))
+                if tuning:
+                    scmd_set_tuning(self.ctx, **tuning)
             for k, th in enumerate(thermostats or []):
                 if th is not None:
                     self.set_thermostat(k, th)

@@ -61,3 +61,19 @@ def test_committed_table_covers_the_benchmark_workloads():
         if t["pairs"] == 1:
             assert (t["ipt"], t["waves_i"], t["waves_j"]) in autotune.SHAPES
     assert all("ms_per_step" in e and "workload" in e for e in table.values())
+    w = inputs.by_name("ni48077_cell")
+    t = autotune.lookup(w.offsets, w.precision, cell=True)
+    assert t is not None and set(t) == {"cell_skin"} and t["cell_skin"] in autotune.CELL_SKINS
+
+
+def test_cell_list_layouts_have_their_own_key_and_skin_entries(tmp_path):
+    import json
+    off = np.array([0, 48077])
+    assert autotune.bucket(off, "fp64", cell=True) != autotune.bucket(off, "fp64")
+    assert autotune.bucket(off, "fp64", cell=True).endswith("/cell")
+    path = tmp_path / "t.json"
+    path.write_text(json.dumps({autotune.bucket(off, "fp64", cell=True):
+                                dict(tuning=dict(cell_skin=0.5), ms_per_step=0.1, workload="x")}))
+    assert autotune.lookup(off, "fp64", str(path), cell=True) == {"cell_skin": 0.5}
+    assert autotune.lookup(off, "fp64", str(path)) is None
+    assert all(0.0 < s < 0.8 for s in autotune.CELL_SKINS)

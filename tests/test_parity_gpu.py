@@ -517,6 +517,22 @@ def test_cell_list_skin_matches_rebuild_every_step(precision):
     assert_forces_close(outs[0][1], f_ref, TOL[precision])
 
 
+def test_cell_skin_from_a_tuning_entry_matches_the_setter():
+    # a tuning entry {"cell_skin": s} (the autotuner's table for the cell
+    # list) sets the same skin as scmd_set_cell_skin: the runs agree bit for bit
+    w = inputs.c2_cooling()
+    outs = []
+    for via_tuning in (True, False):
+        tun = dict(cell_skin=0.3) if via_tuning else None
+        with scmd.Simulation(w.offsets, w.pos, w.vel, dt=2.0, rc=RC, tuning=tun) as sim:
+            if not via_tuning:
+                sim.set_cell_skin(0.3)
+            sim.step(40)
+            outs.append((sim.positions(), sim.forces(), sim.cell_rebuilds()))
+    assert outs[0][2] == outs[1][2] and 1 < outs[0][2] < 41
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_cell_list_checkpoint_resume_is_bitwise():
     # the checkpoint carries the positions of the last rebuild, and restoring
     # it rebuilds those cells and lists: the resumed run repeats the
