@@ -434,7 +434,7 @@ def test_cell_list_batch_with_escaped_atom():
     vel[17] = [70.0, 0.0, 0.0]  # A/fs
     with scmd.Simulation(offsets, pos, vel, dt=1.0, rc=RC) as sim:
         sim.step(12)
-        r = sim.positions()
+        r, v = sim.positions(), sim.velocities()
         sim.compute()
         f, rho = sim.forces(), sim.density()
         ens = [sim.energy(k) for k in range(3)]
@@ -445,6 +445,8 @@ def test_cell_list_batch_with_escaped_atom():
         assert_forces_close(f[lo:hi], f_ref, 1e-10)
         np.testing.assert_allclose(rho[lo:hi], rho_ref, rtol=1e-10, atol=0)
         assert ens[k][0] == pytest.approx(site.sum(), rel=1e-10)
+        # each cluster's kinetic energy from the per-cell v^2 sums of its cells
+        assert ens[k][1] == pytest.approx(oracle.kinetic(v[lo:hi]), rel=1e-12)
     assert ens[1] == (0.0, 0.0, 0.0)
     assert rho[17] == 0.0 and np.all(f[17] == 0.0)
 
