@@ -363,6 +363,8 @@ def main(argv=None):
                 if prec:
                     fw.precision = prec
                 steps = max(32, min(2000, int(2e10 / max(1, _pairs(fw.sizes())))))
+                if fw.rc > 0:
+                    steps = 640  # a cell list rebuilds every few steps: average over many
                 print(f"[bench] form {key}: {fw.n_atoms} atoms, {steps} steps", file=sys.stderr, flush=True)
                 # batches run the launch plan and the cell list the skin that
                 # the autotuner measured for them (paper_1210_3559_amd/tuning_cache.json)
