@@ -634,7 +634,7 @@ int build_plan(scmd_ctx *c, std::vector<ITile> *tiles_out) {
     c->ntiles = (int)tiles.size();
     c->has_split = false;
     for (const ITile &T : tiles) c->has_split = c->has_split || T.nsplit > 1;
-    const size_t part_items = cells ? tiles.size() : items.size();
+    const size_t part_items = cells ? 0 : items.size();  // cell sweeps finish their own atoms
     HIP_TRY(c, c->d_items.ensure(std::max<size_t>(items.size(), 1)));
     HIP_TRY(c, c->d_order.ensure(std::max<size_t>(order.size(), 1)));
     HIP_TRY(c, c->d_tiles.ensure(std::max<size_t>(tiles.size(), 1)));
