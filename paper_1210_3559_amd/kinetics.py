@@ -88,25 +88,35 @@ def escape_rate(lifetimes, censored_at=()):
     return k_mean, k_mle
 
 
-def fit_rate3(T, kappa_per_ps, T0=None, p0=(1.2, 3.0e4, 1030.0)):
+def fit_rate3(T, kappa_per_ps, T0=None, p0=(1.2, 3.0e4, 1030.0), events=None, with_errors: bool = False):
     """Least-squares fit of ln(kappa * 1 ps) = a - b / (k_B T (T - T0)^2)
     (kappa in 1/ps, b in eV K^2); returns (a, b, T0).  With T0 given only a
-    and b are fitted (three temperatures far below T0 do not determine it)."""
+    and b are fitted (three temperatures far below T0 do not determine it).
+    events: the number of observed transitions behind each rate; the fit is
+    then weighted by the rate's statistical error, sigma(ln kappa) =
+    1/sqrt(events) for an exponential lifetime.  with_errors: also return the
+    standard errors of the fitted parameters (from the fit's covariance;
+    absolute when weighted)."""
     from scipy.optimize import curve_fit
     T = np.asarray(T, dtype=np.float64)
     y = np.log(np.asarray(kappa_per_ps, dtype=np.float64))
+    sig = None if events is None else 1.0 / np.sqrt(np.asarray(events, dtype=np.float64))
+    kw = dict(maxfev=20000, sigma=sig, absolute_sigma=sig is not None)
     if T0 is not None:
         def f2(x, a, b):
             return a - b / (K_B * x * (x - T0) ** 2)
 
-        p, _ = curve_fit(f2, T, y, p0=p0[:2], maxfev=20000)
-        return float(p[0]), float(p[1]), float(T0)
+        p, cov = curve_fit(f2, T, y, p0=p0[:2], **kw)
+        res = (float(p[0]), float(p[1]), float(T0))
+        err = (float(np.sqrt(cov[0, 0])), float(np.sqrt(cov[1, 1])), 0.0)
+    else:
+        def f(x, a, b, t0):
+            return a - b / (K_B * x * (x - t0) ** 2)
 
-    def f(x, a, b, t0):
-        return a - b / (K_B * x * (x - t0) ** 2)
-
-    p, _ = curve_fit(f, T, y, p0=p0, maxfev=20000)
-    return tuple(float(v) for v in p)
+        p, cov = curve_fit(f, T, y, p0=p0, **kw)
+        res = tuple(float(v) for v in p)
+        err = tuple(float(np.sqrt(cov[i, i])) for i in range(3))
+    return (res, err) if with_errors else res
 
 
 def structure_series(sim, cluster: int, nframes: int, frame_ps: float, rdf_counts, rdf_nref,

@@ -40,6 +40,26 @@ def test_rate3_fit_reproduces_the_papers_parameters():
     assert math.exp(p["a"]) == pytest.approx(3.5, rel=0.02)
 
 
+def test_weighted_rate3_fit_recovers_exact_parameters_and_reports_errors():
+    # rates that follow Eq. (rate3) exactly: the weighted fit returns the
+    # generating parameters; its standard errors follow sigma(ln k) =
+    # 1/sqrt(events), so four times the events halve them
+    a0, b0, t00 = 1.24, 31053.0, 1029.0
+    T = np.array([780.0, 800.0, 820.0, 830.0, 835.0])
+    k = np.exp(a0 - b0 / (kinetics.K_B * T * (T - t00) ** 2))
+    (a, b, t0), err = kinetics.fit_rate3(T, k, events=[12] * 5, with_errors=True)
+    assert (a, b, t0) == pytest.approx((a0, b0, t00), rel=1e-6)
+    (_, _, _), err4 = kinetics.fit_rate3(T, k, events=[48] * 5, with_errors=True)
+    assert all(e > 0 for e in err)
+    assert np.allclose(np.array(err4), 0.5 * np.array(err), rtol=1e-3)
+    # the paper's own table: T0 within its standard error of 1029 K
+    Tl = [float(x) for x in LT["kappa_1e-5_per_ps"]]
+    kl = [v * 1e-5 for v in LT["kappa_1e-5_per_ps"].values()]
+    nl = [len(LT["lifetimes_ps"][x]) for x in LT["kappa_1e-5_per_ps"]]
+    (_, _, t0l), errl = kinetics.fit_rate3(Tl, kl, events=nl, with_errors=True)
+    assert abs(t0l - LT["fit"]["T0_K"]) < 2.0 * errl[2] + 5.0
+
+
 def test_rate3_fit_with_fixed_t0():
     T = [float(x) for x in LT["kappa_1e-5_per_ps"]]
     k = [v * 1e-5 for v in LT["kappa_1e-5_per_ps"].values()]
