@@ -8,6 +8,7 @@ with ln(kappa * 1 ps) = a - b / (k_B T (T - T0)^2) (Eq. (rate3)).
 
     python -m paper_1210_3559_amd.kinetics --T 780 [--replicas 15]
         [--max-ps 4000] [--T-melt 1400 --melt-ps 100] [--out file.json]
+    python -m paper_1210_3559_amd.kinetics --fit 780.json 800.json ...
 
 Replicas are independent clusters of one batch (own initial velocities and
 bath seeds): they are melted together at T_melt, quenched to T, and stepped
@@ -229,9 +230,29 @@ def run(T: float, replicas: int = 15, max_ps: float = 4000.0, T_melt: float = 14
     }
 
 
+def pooled_rates(results):
+    """Per temperature, the escape rate of all runs of the given results
+    (dicts as returned by run()) pooled: (T, kappa MLE, kappa 1/<t>, events),
+    sorted by T.  The MLE counts runs that had not crystallised at their time
+    limit (censored); 1/<t> uses the observed lifetimes only."""
+    by_T = {}
+    for r in results:
+        d = by_T.setdefault(float(r["T_K"]), ([], []))
+        for x in r["lifetimes_ps"]:
+            (d[0] if x is not None else d[1]).append(float(x) if x is not None else float(r["run_ps"]))
+    out = []
+    for T in sorted(by_T):
+        life, cens = by_T[T]
+        k_mean, k_mle = escape_rate(life, cens)
+        out.append((T, k_mle, k_mean, len(life)))
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--T", type=float, required=True, help="bath temperature, K")
+    ap.add_argument("--fit", nargs="+", default=None, metavar="RESULT_JSON",
+                    help="fit Eq. (rate3) to the pooled rates of these --out files instead of running")
+    ap.add_argument("--T", type=float, default=None, help="bath temperature, K")
     ap.add_argument("--replicas", type=int, default=15)
     ap.add_argument("--max-ps", type=float, default=4000.0)
     ap.add_argument("--seed", type=int, default=820)
@@ -241,6 +262,20 @@ def main(argv=None) -> int:
     ap.add_argument("--melt-ps", type=float, default=100.0, help="length of the melt, ps")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
+    if args.fit:
+        results = []
+        for path in args.fit:
+            with open(path) as f:
+                results.append(json.load(f))
+        rates = pooled_rates(results)
+        T, k, _, ev = zip(*rates)
+        (a, b, t0), err = fit_rate3(T, k, events=ev, with_errors=True)
+        print(json.dumps({"rates": [dict(T_K=t, kappa_mle_per_ps=km, kappa_mean_per_ps=kn, events=e)
+                                    for t, km, kn, e in rates],
+                          "fit": dict(a=a, b_eV_K2=b, T0_K=t0, a_err=err[0], b_err=err[1], T0_err=err[2])}))
+        return 0
+    if args.T is None:
+        ap.error("--T is required unless --fit is given")
     res = run(args.T, args.replicas, args.max_ps, T_melt=args.T_melt, melt_ps=args.melt_ps, seed=args.seed,
               track=args.track, min_ps=args.min_ps)
     if args.out:

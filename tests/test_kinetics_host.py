@@ -120,3 +120,29 @@ def test_structure_series_windows():
     for o in out:
         assert o["rdf_refs"] == 300  # 100 frames x 3 reference atoms
         assert o["D_cm2_per_s"] == pytest.approx(0.2 ** 2 / 20.0 * 1e-4, rel=0.1)
+
+
+def test_pooled_rates_and_fit_cli(tmp_path, capsys):
+    # two result files at one temperature pool their runs (censored ones
+    # count in the MLE); the --fit mode fits the pooled rates
+    r1 = dict(T_K=835.0, run_ps=1000.0, lifetimes_ps=[100.0, None, 300.0])
+    r2 = dict(T_K=835.0, run_ps=2000.0, lifetimes_ps=[None, 500.0])
+    pooled = kinetics.pooled_rates([r1, r2])
+    assert len(pooled) == 1
+    T, k_mle, k_mean, ev = pooled[0]
+    assert (T, ev) == (835.0, 3)
+    assert k_mean == pytest.approx(3 / 900.0)
+    assert k_mle == pytest.approx(3 / (900.0 + 1000.0 + 2000.0))
+    # the paper's Table LT as five result files: the CLI's fit is the weighted fit
+    paths = []
+    for T, life in LT["lifetimes_ps"].items():
+        p = tmp_path / f"{T}.json"
+        p.write_text(json.dumps(dict(T_K=float(T), run_ps=1e9, lifetimes_ps=life)))
+        paths.append(str(p))
+    assert kinetics.main(["--fit"] + paths) == 0
+    out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    Tl = [float(x) for x in LT["lifetimes_ps"]]
+    kl = [1.0 / np.mean(v) for v in LT["lifetimes_ps"].values()]
+    nl = [len(v) for v in LT["lifetimes_ps"].values()]
+    (a, b, t0), _ = kinetics.fit_rate3(Tl, kl, events=nl, with_errors=True)
+    assert out["fit"]["T0_K"] == pytest.approx(t0) and out["fit"]["b_eV_K2"] == pytest.approx(b)
