@@ -255,7 +255,9 @@ def main(argv=None) -> int:
     ap.add_argument("--T", type=float, default=None, help="bath temperature, K")
     ap.add_argument("--replicas", type=int, default=15)
     ap.add_argument("--max-ps", type=float, default=4000.0)
-    ap.add_argument("--seed", type=int, default=820)
+    ap.add_argument("--seed", type=int, default=820,
+                    help="replica k takes its velocities from seed + 1 + k and its bath from seed + k: "
+                         "independent runs need seeds at least --replicas + 1 apart")
     ap.add_argument("--track", type=int, default=0, help="replicas whose D(t) and g(r) are recorded")
     ap.add_argument("--min-ps", type=float, default=0.0, help="run at least this long")
     ap.add_argument("--T-melt", type=float, default=1400.0, help="bath temperature of the melt, K")
