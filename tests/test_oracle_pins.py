@@ -18,7 +18,9 @@ from paper_1210_3559_amd import inputs
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "reference_values.json")))
 SC = GOLDEN["sutton_chen_ni"]
 EPS, A, C, NEXP, MEXP = SC["eps_eV"], SC["a_A"], SC["c"], SC["n"], SC["m"]
-NT = min(8, os.cpu_count() or 1)
+# oracle threads: the cores shared out over pytest-xdist workers, if any (the
+# trajectory tests meet an OpenMP barrier every step and crawl when oversubscribed)
+NT = max(1, min(8, os.cpu_count() or 1) // int(os.environ.get("PYTEST_XDIST_WORKER_COUNT", "1")))
 
 # CODATA 2018: elementary charge (exact) and atomic mass constant; k_B (exact).
 E_CHARGE = 1.602176634e-19
