@@ -158,7 +158,9 @@ int scmd_destroy(scmd_ctx *ctx);
  * atoms of each cluster inside pos and vel (host, offsets[n_clusters] x 3
  * doubles, A and A/fs).  vel may be NULL (all zero).  mass_u > 0 is the atomic
  * mass (58.6934 for Ni).  The total atom count must be below 2^30.  Copies the
- * data to the device; the caller's arrays may be reused at return. */
+ * data to the device; the caller's arrays may be reused at return.  A batch
+ * holds the paper's ensembles of independent runs of one cluster (Sec. 3,
+ * "Kinetics of the solidification phase transition", Table LT). */
 int scmd_init_clusters(scmd_ctx *ctx, int n_clusters, const int64_t *offsets, const double *pos,
                        const double *vel, double mass_u);
 
@@ -218,7 +220,9 @@ int scmd_set_langevin(scmd_ctx *ctx, int cluster, double T_start_K, double T_end
  * is then still listed; the pair terms apply rc themselves).  skin = 0
  * rebuilds every step.  Results are the same up to summation order (the
  * order of a list's entries).  SCMD_EINVAL for a negative or non-finite
- * skin; takes effect at the next evaluation. */
+ * skin; takes effect at the next evaluation.  The paper sums over all pairs
+ * and leaves a cutoff to later work (Sec. 2, "Computational approach"): the
+ * cell list and its skin are this library's. */
 int scmd_set_cell_skin(scmd_ctx *ctx, double skin_A);
 
 /* Rebuilds of the cell list's cells and lists since it was planned (the
@@ -227,7 +231,9 @@ int scmd_set_cell_skin(scmd_ctx *ctx, double skin_A);
  * context stream. */
 int scmd_get_cell_rebuilds(scmd_ctx *ctx, int64_t *rebuilds);
 
-/* Override the sweep launch shape (NULL restores defaults). */
+/* Override the sweep launch shape (NULL restores defaults).  These shapes
+ * replace the paper's one-atom-per-thread GPU scheme (Sec. 2, "Computational
+ * approach"); every shape computes the same sums up to summation order. */
 int scmd_set_tuning(scmd_ctx *ctx, const scmd_tuning *tuning);
 
 /* Evaluate rho_i (Sec. 2.1, Eq. (rho)), the forces -grad U of Eq. (SC) and
