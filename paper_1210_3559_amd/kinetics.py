@@ -218,7 +218,7 @@ def run(T: float, replicas: int = 15, max_ps: float = 4000.0, T_melt: float = 14
             sol = np.median(ek[tk >= tk[-1] - 30.0])
             lat.append(float(liq - sol) * n)
     return {
-        "T_K": T, "replicas": replicas, "atoms_per_cluster": n, "gamma_per_ps": gamma, "dt_fs": dt,
+        "T_K": T, "replicas": replicas, "seed": seed, "atoms_per_cluster": n, "gamma_per_ps": gamma, "dt_fs": dt,
         "tracked": series,
         "melt": {"T_K": T_melt, "ps": melt_steps * dt * 1e-3}, "max_ps": max_ps, "run_ps": run_ps,
         "lifetimes_ps": [x for x in found], "n_crystallised": len(life), "mean_lifetime_ps": (
@@ -230,11 +230,29 @@ def run(T: float, replicas: int = 15, max_ps: float = 4000.0, T_melt: float = 14
     }
 
 
+def _shared_replicas(r1, r2) -> bool:
+    """Whether two results repeat a replica: replica k of a run with base seed
+    s takes its velocities from s + 1 + k and its bath from s + k, so two runs
+    of one protocol share a replica exactly when their seeds differ by less
+    than the replica count of the run with the lower seed."""
+    keys = ("T_K", "gamma_per_ps", "dt_fs", "melt")
+    if "seed" not in r1 or "seed" not in r2 or any(r1.get(k) != r2.get(k) for k in keys):
+        return False
+    d = int(r2["seed"]) - int(r1["seed"])
+    return -int(r2["replicas"]) < d < int(r1["replicas"])
+
+
 def pooled_rates(results):
     """Per temperature, the escape rate of all runs of the given results
     (dicts as returned by run()) pooled: (T, kappa MLE, kappa 1/<t>, events),
     sorted by T.  The MLE counts runs that had not crystallised at their time
-    limit (censored); 1/<t> uses the observed lifetimes only."""
+    limit (censored); 1/<t> uses the observed lifetimes only.  Raises
+    ValueError for two results that repeat a replica (seeds too close)."""
+    for i, r1 in enumerate(results):
+        for r2 in results[i + 1:]:
+            if _shared_replicas(r1, r2):
+                raise ValueError(f"runs at {r1['T_K']} K with seeds {r1['seed']} and {r2['seed']} repeat replicas: "
+                                 f"seeds of one protocol need to be at least the replica count apart")
     by_T = {}
     for r in results:
         d = by_T.setdefault(float(r["T_K"]), ([], []))

@@ -146,3 +146,23 @@ def test_pooled_rates_and_fit_cli(tmp_path, capsys):
     nl = [len(v) for v in LT["lifetimes_ps"].values()]
     (a, b, t0), _ = kinetics.fit_rate3(Tl, kl, events=nl, with_errors=True)
     assert out["fit"]["T0_K"] == pytest.approx(t0) and out["fit"]["b_eV_K2"] == pytest.approx(b)
+
+
+def test_pooling_refuses_runs_that_repeat_replicas():
+    # replica k of seed s: velocities s + 1 + k, bath s + k; seeds 8351 and
+    # 8352 with 12 replicas each repeat 11 replicas, 8351 and 8363 none
+    melt = {"T_K": 1400.0, "ps": 100.0}
+    base = dict(T_K=835.0, replicas=12, gamma_per_ps=10.0, dt_fs=1.0, melt=melt, run_ps=1000.0,
+                lifetimes_ps=[None] * 12)
+    a, b, c = dict(base, seed=8351), dict(base, seed=8352), dict(base, seed=8363)
+    with pytest.raises(ValueError, match="repeat replicas"):
+        kinetics.pooled_rates([a, b])
+    with pytest.raises(ValueError, match="repeat replicas"):
+        kinetics.pooled_rates([c, dict(base, seed=8352)])
+    assert kinetics.pooled_rates([a, c])[0][3] == 0
+    # another temperature, another melt or a result without its seed: no shared replica
+    kinetics.pooled_rates([a, dict(b, T_K=830.0)])
+    kinetics.pooled_rates([a, dict(b, melt={"T_K": 1800.0, "ps": 400.0})])
+    nos = dict(b)
+    del nos["seed"]
+    kinetics.pooled_rates([a, nos])
